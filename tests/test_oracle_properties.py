@@ -1,0 +1,450 @@
+"""Pins of the oracle against what the paper proves and what mathematics fixes:
+
+* hand-computed residuals on one- and two-cell meshes (brute force),
+* well-balancing / lake at rest, also over discontinuous and emerging beds
+  and hanging faces (Def. 3.1, Prop. 3.1, Table 3),
+* mass conservation on static meshes (Sec. 3.4, Sec. 4.3),
+* positivity of the element mass under the CFL bound (Props. 3.2 and 3.3)
+  and its violation far above it,
+* consistency with continuity of the tracer (Sec. 3.4),
+* design order on the travelling vortex (Sec. 4.4) with the GLL sub-grid rule,
+* the Ritter dam break on a flat dry bed,
+* Manning friction decay of a uniform flow (closed form),
+* mirror and transpose symmetry,
+* all-wet Newton converging in one iteration (Sec. 3.3).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from exact import Vortex, manning_decay, ritter
+from oracle import Mesh, Oracle, Params, gl_rule, tensor_basis
+
+G = 9.81
+
+
+def make(mesh, p, depth_fn=None, depth=None):
+    o = Oracle(mesh, p)
+    xy = o.node_coords()
+    if depth is None:
+        depth = depth_fn(xy[:, 0], xy[:, 1])
+    o.set_bathymetry(-np.asarray(depth))      # the oracle takes bed elevation b = -zb
+    return o, xy
+
+
+# ---------------------------------------------------------------------------
+# brute force on tiny meshes
+# ---------------------------------------------------------------------------
+
+def test_single_cell_uniform_flow_against_walls():
+    """One cell, walls, r=1, EQ_3, depth 1, zeta 0, q = (q0, 0): closed form by hand.
+
+    F_i = -+ q0 dx/2 (volume only; wall mass flux vanishes);
+    Gx_i = -(q0^2 + sqrt(g) q0) dx/2 on all four nodes (advective volume term plus
+    the Rusanov momentum flux against the mirrored wall state)."""
+    dx, q0 = 2.0, 0.3
+    m = Mesh.uniform(1, 1, 0.0, 0.0, dx)
+    o, _ = make(m, Params(r=1, S=(3,), rule="eq", eps=1e-3), depth=np.ones(9))
+    st = [np.zeros((1, 4)), np.full((1, 4), q0), np.zeros((1, 4)), np.zeros((1, 4))]
+    F, Gx, Gy, R, dtb = o.apply_operator(st, 0.0)
+    sx = np.array([-1, 1, -1, 1])             # sign of d psi_j / dx, j = jy*2 + jx
+    assert np.allclose(F[0], sx * q0 * dx / 2, atol=1e-14)
+    assert np.allclose(Gx[0], -(q0 ** 2 + math.sqrt(G) * q0) * dx / 2, atol=1e-13)
+    assert np.allclose(Gy[0], 0.0, atol=1e-14)
+    assert dtb == pytest.approx(dx / (q0 + math.sqrt(G)), rel=1e-14)
+
+
+def test_two_cells_surface_step_pressure_and_rusanov():
+    """Two cells, depth 1, zeta = 0.1 | 0, q = 0.  Only the interior face acts:
+    mass flux lam/2 (zeta*A - zeta*B), pressure 1/2 g avg(h*) [zeta*] on BOTH sides."""
+    dx = 1.0
+    m = Mesh.uniform(2, 1, 0.0, 0.0, dx)
+    o, _ = make(m, Params(r=1, S=(3,), rule="eq", eps=1e-3), depth=np.ones(18))
+    zeta = np.array([[0.1] * 4, [0.0] * 4])
+    z = np.zeros((2, 4))
+    F, Gx, Gy, R, _ = o.apply_operator([zeta, z, z, z], 0.0)
+    lam = math.sqrt(G * 1.1)
+    flux = 0.5 * lam * 0.1
+    pres = 0.5 * G * 0.5 * (1.1 + 1.0) * 0.1
+    east = np.array([0, 1, 0, 1])             # nodes jx = 1 of the left cell
+    west = 1 - east
+    assert np.allclose(F[0], -flux * dx / 2 * east, atol=1e-14)
+    assert np.allclose(F[1], flux * dx / 2 * west, atol=1e-14)
+    assert np.allclose(Gx[0], pres * dx / 2 * east, atol=1e-14)
+    assert np.allclose(Gx[1], pres * dx / 2 * west, atol=1e-14)
+    assert np.allclose(Gy, 0.0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# lake at rest (Def. 3.1, Prop. 3.1, Table 3)
+# ---------------------------------------------------------------------------
+
+def e1_depth(x, y, zb0=0.65):
+    """Submerged discontinuous bed of Sec. 4.1 (second (x-0.5) read as (y-0.5))."""
+    box = (x > 0.9) & (x < 1.1) & (y > 0.3) & (y < 0.7)
+    psi = np.where(box, np.sqrt((x - 0.9) ** 2 + (y - 0.5) ** 2),
+                   -5 * (x - 0.9) ** 2 - 50 * (y - 0.5) ** 2)
+    return -zb0 * np.exp(psi)
+
+
+def e2_depth(x, y):
+    """Partially submerged smooth bed of Sec. 4.1 (wet/dry)."""
+    return -1.3 * np.exp(-5 * (x - 0.9) ** 2 - 50 * (y - 0.5) ** 2)
+
+
+def nudged_depth(o, fn):
+    """Sample each node nudged 1e-9 into its own cell, so a jump on a cell edge gives
+    different bed values on the two sides of the face."""
+    xy = o.node_coords()
+    cx = np.repeat(o.m.xc + o.m.dx / 2, [o.level_of[int(L)].S ** 2 for L in o.m.level])
+    cy = np.repeat(o.m.yc + o.m.dx / 2, [o.level_of[int(L)].S ** 2 for L in o.m.level])
+    x = xy[:, 0] + 1e-9 * np.sign(cx - xy[:, 0])
+    y = xy[:, 1] + 1e-9 * np.sign(cy - xy[:, 1])
+    return fn(x, y)
+
+
+@pytest.mark.parametrize("r,S,rule,mesh_n", [(1, 8, "eq", (40, 20)), (2, 4, "gll", (40, 20)),
+                                             (3, 8, "eq", (37, 19))])
+def test_lake_at_rest_discontinuous_submerged(r, S, rule, mesh_n):
+    nx, ny = mesh_n
+    m = Mesh.uniform(nx, ny, 0.0, 0.0, 2.0 / nx)
+    # CFL below the linear-stability limit 1/(2r+1) quoted in Table 2
+    o = Oracle(m, Params(r=r, S=(S,), rule=rule, rk="rk32", eps=1e-3, h_lim=1e-3, cfl=0.2 / 2 ** (r - 1)))
+    o.set_bathymetry(-nudged_depth(o, e1_depth))
+    o.init_lake_at_rest(np.ones((m.K, (r + 1) ** 2)))
+    F, Gx, Gy, _, _ = o.apply_operator()
+    scale = G * m.dx[0]
+    assert np.abs(F).max() < 1e-14 * scale and np.abs(Gx).max() < 1e-13 * scale
+    for _ in range(10):
+        o.step()
+    z, qx, qy, _ = o.get_state()
+    assert np.abs(z - 1.0).max() < 1e-13
+    assert max(np.abs(qx).max(), np.abs(qy).max()) < 1e-13
+
+
+@pytest.mark.parametrize("r,S", [(1, 6), (2, 8), (3, 8)])
+def test_lake_at_rest_wet_dry(r, S):
+    m = Mesh.uniform(40, 20, 0.0, 0.0, 0.05)
+    o, _ = make(m, Params(r=r, S=(S,), rule="eq", rk="rk32", eps=1e-3, h_lim=1e-3, cfl=0.2 / 2 ** (r - 1)),
+                e2_depth)
+    o.init_lake_at_rest(np.ones((m.K, (r + 1) ** 2)))
+    z0 = o.get_state()[0]
+    Hn0 = o.depth_integrals()
+    dry = Hn0.sum(1) == 0
+    assert dry.any() and (~dry).any()
+    for _ in range(10):
+        d = o.step()
+    z, qx, qy, _ = o.get_state()
+    assert np.abs(z[~dry] - z0[~dry]).max() < 1e-13
+    assert max(np.abs(qx).max(), np.abs(qy).max()) < 1e-13
+    # dry cells stay dry (compare depths, not the non-unique dry surface)
+    assert np.abs(o.depth_integrals()[dry]).max() < 1e-15
+    assert d["n_r0"] > 0
+
+
+# ---------------------------------------------------------------------------
+# mass, positivity and CWC on a wet/dry dam break over a beach with cuts
+# ---------------------------------------------------------------------------
+
+def beach_case(r=2, S=6, rk="ssp3", cfl=0.9, mode=1, tracer=False, nx=24, ny=8):
+    L = 2400.0
+    dx = L / nx
+    m = Mesh.uniform(nx, ny, 0.0, 0.0, dx)
+
+    def depth(x, y):
+        bed = -4.0 + 6.0 * x / L + 0.3 * np.sin(x / 97.0) * np.cos(y / 61.0)
+        bed = np.where(np.abs(y - 430.0) < 40.0, bed - 1.0, bed)   # a discontinuous cut
+        return -bed
+
+    p = Params(r=r, S=(S,), rule="eq", rk=rk, eps=0.05, h_lim=0.05, cfl=cfl, cfl_mode=mode, tracer=tracer)
+    o, _ = make(m, p, depth)
+    dof = o.dof_coords()
+    eta = np.where(dof[..., 0] < 900.0, 1.0, 0.0)
+    o.set_state(eta, np.zeros_like(eta), np.zeros_like(eta), np.ones_like(eta))
+    o.init_lake_at_rest(eta)
+    o.state[3] = torch.ones_like(o.state[3])
+    o.set_manning(np.full(m.K, 0.02))
+    return o
+
+
+def test_mass_conservation_and_positivity_under_bound():
+    o = beach_case()
+    m0 = o.total_mass()
+    worst = np.inf
+    its = 0
+    for _ in range(25):
+        d = o.step()
+        worst = min(worst, d["min_target"])
+        its = max(its, d["newton_it"])
+        assert d["n_viol"] == 0
+    assert abs(o.total_mass() - m0) / m0 < 1e-13
+    assert worst >= 0.0
+    assert its <= 4
+
+
+@pytest.mark.parametrize("rk,fac", [("fe", 1.0), ("rk32", None), ("ssp3", 1.0)])
+def test_positivity_at_the_bound(rk, fac):
+    """Prop. 3.2 (FE, dt <= w1 J/(lam l)) and Prop. 3.3 (dt <= dt_FE / a21)."""
+    from oracle import tableau
+    if fac is None:
+        fac = 1.0 / tableau(rk)[0][1][0]
+    o = beach_case(r=1, S=4, rk=rk, cfl=fac, mode=1)
+    for _ in range(15):
+        d = o.step()
+        assert d["min_target"] >= -1e-12
+        assert d["n_viol"] == 0
+
+
+def perched_cell(rk, cfl):
+    """A 1 cm layer on a raised cell (bed +1 m) inside deep water (bed -2 m, zeta 0):
+    the raised cell drains through all four faces at once."""
+    m = Mesh.uniform(5, 5, 0.0, 0.0, 10.0)
+    p = Params(r=1, S=(4,), rule="eq", rk=rk, eps=1e-3, h_lim=1e-3, cfl=cfl, cfl_mode=1)
+    o = Oracle(m, p)
+    bed = np.full((m.K, 16), -2.0)
+    bed[12] = 1.0
+    o.set_bathymetry(bed.ravel())
+    eta = np.zeros((m.K, 4))
+    eta[12] = 1.01
+    o.set_state(eta, np.zeros_like(eta), np.zeros_like(eta))
+    return o
+
+
+@pytest.mark.parametrize("cfl,expect_violation", [(1.0, False), (0.5, False), (30.0, True)])
+def test_positivity_perched_cell(cfl, expect_violation):
+    """Prop. 3.2: at dt <= w1 J/(lam l) the element mass stays non-negative; far
+    above the bound the raised cell loses more than it holds."""
+    o = perched_cell("fe", cfl)
+    d = o.step()
+    assert (d["n_viol"] > 0) == expect_violation
+    if not expect_violation:
+        assert d["min_target"] >= 0.0
+
+
+def test_consistency_with_continuity():
+    """c = 1 stays 1 to roundoff (Sec. 3.4, eq:cwc1) through wet/dry fronts."""
+    o = beach_case(tracer=True)
+    for _ in range(15):
+        o.step()
+    c = o.get_state()[3]
+    assert np.abs(c - 1.0).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# convergence on the travelling vortex (Sec. 4.4) with the GLL rule
+# ---------------------------------------------------------------------------
+
+def vortex_error(N, r, S, T=0.05, cfl=0.1, rk="ssp3", mesh=None):
+    m = mesh or Mesh.uniform(2 * N, N, 0.0, 0.0, 1.0 / N, bc=("periodic", "periodic", "wall", "wall"))
+    p = Params(r=r, S=(S,) * (int(m.level.max()) + 1), rule="gll", rk=rk, eps=1e-3, h_lim=0.0,
+               cfl=cfl, adapt_degree=False)
+    o, _ = make(m, p, depth=None, depth_fn=lambda x, y: np.zeros_like(x))
+    v = Vortex()
+    d = o.dof_coords()
+    h, u, w = v.fields(d[..., 0], d[..., 1], 0.0, period_x=2.0)
+    o.set_state(h, h * u, h * w)
+    dxmin = float(m.dx.min())
+    dt0 = cfl * dxmin / (6.9 + math.sqrt(G))
+    nst = int(math.ceil(T / dt0))
+    for _ in range(nst):
+        o.step(T / nst)
+    xg, wg = gl_rule(r + 3)
+    X, Y = np.tile(xg, r + 3), np.repeat(xg, r + 3)
+    B, _, _ = tensor_basis(r, X, Y)
+    z = o.state[0].numpy() @ B.T
+    xs = m.xc[:, None] + X[None] * m.dx[:, None]
+    ys = m.yc[:, None] + Y[None] * m.dx[:, None]
+    he, _, _ = v.fields(xs, ys, T, period_x=2.0)
+    w2 = np.outer(wg, wg).ravel()
+    return math.sqrt(np.sum(w2[None] * m.dx[:, None] ** 2 * (z - he) ** 2)), o
+
+
+@pytest.mark.parametrize("r,S,Ns,rate", [(1, 4, (16, 32), 1.8), (2, 5, (8, 16), 2.8)])
+def test_vortex_design_order(r, S, Ns, rate):
+    e1, _ = vortex_error(Ns[0], r, S)
+    e2, _ = vortex_error(Ns[1], r, S)
+    assert math.log2(e1 / e2) > rate, (e1, e2)
+
+
+def test_vortex_on_hanging_mesh():
+    """A band of refined cells across the vortex path (2:1 hanging faces): the
+    error lies between the coarse and the fine uniform errors and mass is kept."""
+    from workloads import quadtree_desc
+    N = 8
+
+    def refine(L, cand):
+        if L > 0:
+            return []
+        return [c for c in cand if 4 <= c[1] < 10 and 2 <= c[2] < 6]
+
+    d = quadtree_desc(2 * N, N, 0.0, 0.0, 1.0 / N, refine, 1, bc=("periodic", "periodic", "wall", "wall"))
+    m = Mesh(d["nx0"], d["ny0"], d["x0"], d["y0"], d["dx0"], d["level"], d["i"], d["j"], d["bc"])
+    assert any(f[4] >= 0 for f in m.faces)
+    e_h, o = vortex_error(N, 1, 4, mesh=m)
+    e_c, _ = vortex_error(N, 1, 4)
+    e_f, _ = vortex_error(2 * N, 1, 4)
+    assert e_f < e_h < e_c
+
+
+def test_lake_at_rest_on_hanging_mesh():
+    from workloads import quadtree_desc
+
+    def refine(L, cand):
+        return [c for c in cand if (c[1] + 2 * c[2]) % 3 == 0]
+
+    d = quadtree_desc(8, 4, 0.0, 0.0, 0.25, refine, 2)
+    m = Mesh(d["nx0"], d["ny0"], d["x0"], d["y0"], d["dx0"], d["level"], d["i"], d["j"], d["bc"])
+    assert sum(1 for f in m.faces if f[4] >= 0) > 10
+    o = Oracle(m, Params(r=2, S=(16, 8, 4), rule="eq", rk="ssp3", eps=1e-3, h_lim=1e-3, cfl=0.05))
+    o.set_bathymetry(-nudged_depth(o, e2_depth))
+    o.init_lake_at_rest(np.ones((m.K, 9)))
+    z0 = o.get_state()[0]
+    dry = o.depth_integrals().sum(1) == 0
+    m0 = o.total_mass()
+    for _ in range(8):
+        o.step()
+    z, qx, qy, _ = o.get_state()
+    assert np.abs(z[~dry] - z0[~dry]).max() < 1e-13
+    assert max(np.abs(qx).max(), np.abs(qy).max()) < 1e-13
+    assert abs(o.total_mass() - m0) / m0 < 1e-14
+
+
+def test_mass_conservation_hanging_dambreak():
+    from workloads import quadtree_desc
+
+    def refine(L, cand):
+        return [c for c in cand if (c[1] * 7 + c[2] * 3) % 4 == 0]
+
+    d = quadtree_desc(8, 4, 0.0, 0.0, 100.0, refine, 2)
+    m = Mesh(d["nx0"], d["ny0"], d["x0"], d["y0"], d["dx0"], d["level"], d["i"], d["j"], d["bc"])
+    p = Params(r=1, S=(12, 6, 3), rule="eq", rk="ssp3", eps=0.05, h_lim=0.05, cfl=0.9, cfl_mode=1, tracer=True)
+    o, _ = make(m, p, lambda x, y: 3.0 - 4.0 * x / 800.0 + 0.5 * np.sin(y / 50.0))
+    dof = o.dof_coords()
+    eta = np.where(dof[..., 0] < 350.0, 1.0, 0.0)
+    o.init_lake_at_rest(eta)
+    o.state[3] = torch.ones_like(o.state[3])
+    m0 = o.total_mass()
+    for _ in range(20):
+        d_ = o.step()
+    assert abs(o.total_mass() - m0) / m0 < 1e-13
+    assert np.abs(o.get_state()[3] - 1.0).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Ritter dam break, friction decay, symmetry, Newton
+# ---------------------------------------------------------------------------
+
+def ritter_run(N, T=15.0):
+    """Dam break of 1 m onto a dry flat bed in a 1 km strip (walls far away)."""
+    Lx, xd, h0 = 1000.0, 500.0, 1.0
+    m = Mesh.uniform(N, 1, 0.0, 0.0, Lx / N)
+    p = Params(r=1, S=(4,), rule="eq", rk="ssp3", eps=1e-2, h_lim=1e-2, cfl=0.9, cfl_mode=1)
+    o, _ = make(m, p, depth_fn=lambda x, y: np.zeros_like(x))
+    dof = o.dof_coords()
+    o.init_lake_at_rest(np.where(dof[..., 0] < xd, h0, 0.0))
+    m0 = o.total_mass()
+    while o.t < T - 1e-12:
+        dtb = o.apply_operator()[4] * 0.9 * (1.0 / 6.0)
+        d = o.step(min(dtb, T - o.t))
+        assert d["n_viol"] == 0
+    hbar = o.depth_integrals().sum(1) / m.dx ** 2          # cell-mean depth
+    xc = m.xc + m.dx / 2
+    he, _ = ritter(xc, T, h0, xd)
+    l1 = float(np.sum(np.abs(hbar - he) * m.dx))
+    front = float((m.xc + m.dx)[hbar > 0.05].max())
+    front_ex = float(xc[he > 0.05].max())
+    return l1, front, front_ex, abs(o.total_mass() - m0) / m0, m.dx[0]
+
+
+def test_ritter_dam_break():
+    l1a, _, _, dma, _ = ritter_run(40)
+    l1b, fb, fexb, dmb, dxb = ritter_run(80)
+    assert l1b < 0.6 * l1a
+    assert dma < 1e-13 and dmb < 1e-13
+    assert abs(fb - fexb) <= 2 * dxb
+
+
+def test_manning_decay_of_uniform_flow():
+    m = Mesh.uniform(3, 3, 0.0, 0.0, 10.0, bc=("periodic",) * 4)
+    p = Params(r=1, S=(4,), rule="eq", rk="ssp3", eps=1e-3, h_lim=1e-3, adapt_degree=False)
+    o, _ = make(m, p, depth_fn=lambda x, y: np.full_like(x, 2.0))
+    q0x, q0y, nman = 1.0, 0.5, 0.05
+    z = np.zeros((m.K, 4))
+    o.set_state(z, np.full_like(z, q0x), np.full_like(z, q0y))
+    o.set_manning(np.full(m.K, nman))
+    T, nst = 100.0, 500          # dt = 0.2 s: CFL 0.1, inside linear stability
+    for _ in range(nst):
+        o.step(T / nst)
+    _, qx, qy, _ = o.get_state()
+    q0 = math.hypot(q0x, q0y)
+    qe = manning_decay(q0, 2.0, nman, T)
+    assert np.allclose(qx, qe * q0x / q0, rtol=1e-9)
+    assert np.allclose(qy, qe * q0y / q0, rtol=1e-9)
+    assert np.abs(o.get_state()[0]).max() < 1e-12
+
+
+def _perm_mirror_x(nx, ny, r, S):
+    """cell and node permutations of x -> L - x on a uniform grid."""
+    cells = np.array([(j * nx + (nx - 1 - i)) for j in range(ny) for i in range(nx)])
+    dofs = np.array([jy * (r + 1) + (r - jx) for jy in range(r + 1) for jx in range(r + 1)])
+    nodes = np.array([b * S + (S - 1 - a) for b in range(S) for a in range(S)])
+    return cells, dofs, nodes
+
+
+def _perm_transpose(n, r, S):
+    cells = np.array([(i * n + j) for j in range(n) for i in range(n)])
+    dofs = np.array([jx * (r + 1) + jy for jy in range(r + 1) for jx in range(r + 1)])
+    nodes = np.array([a * S + b for b in range(S) for a in range(S)])
+    return cells, dofs, nodes
+
+
+@pytest.mark.parametrize("kind", ["mirror", "transpose"])
+def test_symmetry(kind):
+    n, r, S = 8, 2, 6
+    m = Mesh.uniform(n, n, 0.0, 0.0, 100.0)
+    p = Params(r=r, S=(S,), rule="eq", rk="ssp3", eps=0.05, h_lim=0.05, cfl=0.5, cfl_mode=1)
+    rng = np.random.default_rng(3)
+    o1, xy = make(m, p, lambda x, y: 1.0 - 2.0 * x / 800 + 0.7 * np.sin(x / 37.0 + y / 23.0))
+    b1 = -(1.0 - 2.0 * xy[:, 0] / 800 + 0.7 * np.sin(xy[:, 0] / 37.0 + xy[:, 1] / 23.0))
+    cells, dofs, nodes = _perm_mirror_x(n, n, r, S) if kind == "mirror" else _perm_transpose(n, r, S)
+    eta = rng.uniform(-0.2, 0.6, (m.K, (r + 1) ** 2))
+    qx = rng.uniform(-0.3, 0.3, eta.shape)
+    qy = rng.uniform(-0.3, 0.3, eta.shape)
+    o1.set_manning(np.full(m.K, 0.03))
+    o1.set_state(eta, qx, qy)
+    o2 = Oracle(m, p)
+    bb = b1.reshape(m.K, S * S)[cells][:, nodes].ravel()
+    o2.set_bathymetry(bb)
+    o2.set_manning(np.full(m.K, 0.03))
+    pe = lambda a: a[cells][:, dofs]
+    if kind == "mirror":
+        o2.set_state(pe(eta), -pe(qx), pe(qy))
+    else:
+        o2.set_state(pe(eta), pe(qy), pe(qx))
+    for _ in range(4):
+        o1.step()
+        o2.step()
+    s1, s2 = o1.get_state(), o2.get_state()
+    if kind == "mirror":
+        assert np.allclose(pe(s1[0]), s2[0], atol=1e-12)
+        assert np.allclose(-pe(s1[1]), s2[1], atol=1e-12)
+        assert np.allclose(pe(s1[2]), s2[2], atol=1e-12)
+    else:
+        assert np.allclose(pe(s1[0]), s2[0], atol=1e-12)
+        assert np.allclose(pe(s1[1]), s2[2], atol=1e-12)
+        assert np.allclose(pe(s1[2]), s2[1], atol=1e-12)
+
+
+def test_all_wet_newton_single_iteration():
+    """Sec. 3.3: with no wet/dry interface the first Newton iterate is the root."""
+    m = Mesh.uniform(6, 6, 0.0, 0.0, 50.0)
+    p = Params(r=3, S=(8,), rule="eq", rk="ssp3", eps=0.05, h_lim=0.05, cfl=0.8, cfl_mode=1)
+    o, _ = make(m, p, lambda x, y: 5.0 + 0.5 * np.cos(x / 30.0) * np.sin(y / 20.0))
+    dof = o.dof_coords()
+    eta = 0.2 * np.exp(-((dof[..., 0] - 150) ** 2 + (dof[..., 1] - 150) ** 2) / 80.0 ** 2)
+    o.set_state(eta, np.zeros_like(eta), np.zeros_like(eta))
+    for _ in range(5):
+        d = o.step()
+        assert d["newton_it"] == 1
