@@ -1,0 +1,174 @@
+/*
+ * sw.h -- C ABI of the MI355X (gfx950) library for the discontinuous-Galerkin
+ * shallow-water operator with sub-grid bathymetry of Arpaia, Orlando, Ferrarin
+ * and Bonaventura, arXiv:2505.18743.
+ *
+ * The library advances
+ *     dh/dt + div q = 0,  dq/dt + div(q (x) u) + g h grad zeta = -gamma q,
+ *     d(hc)/dt + div(q c) = 0                               (Sec. 2, eq:shw)
+ * with h = max(zeta - b, 0) evaluated only at quadrature nodes (eq:zeta2depth-2),
+ * nodal Q_r elements on GLL support points (Sec. 3.2), Rusanov fluxes with
+ * hydrostatic reconstruction (eq:lxf_parameter, eq:hydro_rec_vars), the
+ * non-conservative pressure form (eq:discharge_rhs, eq:pressure_tumolo), an
+ * element-wise Newton solve for the free surface with a land-sea-mask Jacobian
+ * (eq:newton, eq:mass_matrix), degree coarsening to r_K = 0 at wet/dry
+ * elements (eq:criteria_p) and an hc-consistent tracer update
+ * (eq:algebraic_concentration), in the explicit Butcher form of Sec. 3.1.
+ *
+ * Conventions (all calls):
+ *  - All real data are IEEE double.  "device" pointers are HIP device (or
+ *    managed) memory on the device that was current at sw_create; "host"
+ *    pointers are ordinary host memory.  Arrays are copied in or out during
+ *    the call; the caller keeps ownership of every buffer it passes.
+ *  - Nodal fields use the layout [cell][jy][jx] with (r+1)^2 values per cell,
+ *    jx, jy indexing the (r+1)-point GLL support points on [0,1] (Sec. 3.2).
+ *  - Sample-node fields use [cell][b][a] with S_L^2 values for a cell of
+ *    level L: node (a, b) sits at x = x0 + (i + xhat_a) dx_L,
+ *    y = y0 + (j + xhat_b) dx_L, xhat the closed S_L-point rule on [0,1].
+ *    The same formula gives bitwise-equal coordinates on both sides of every
+ *    face, so a single-valued bed yields equal samples there.
+ *  - Cells must be given sorted by level (non-decreasing).
+ *  - Calls enqueue work on the context's stream and return without waiting,
+ *    except where marked "synchronises".
+ *  - Every call returns an sw_status; on failure sw_last_error() returns a
+ *    message (thread-local, valid until the next failing call on the thread).
+ *    No C++ exception crosses this interface.
+ *  - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef SW_H_
+#define SW_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sw_ctx sw_ctx;
+
+typedef enum {
+  SW_OK = 0,
+  SW_EINVAL = -1,       /* invalid argument (message says which)            */
+  SW_ENOMEM = -2,       /* device allocation failed                          */
+  SW_EHIP = -3,         /* a HIP runtime call failed                         */
+  SW_ENONFINITE = -4,   /* a non-finite value appeared in the state          */
+  SW_EDEVICE = -5       /* a kernel detected an invalid index and skipped it */
+} sw_status;
+
+/* boundary kinds for the four sides of the domain (west, east, south, north) */
+enum { SW_BC_WALL = 0,      /* ghost mirrors the normal discharge                  */
+       SW_BC_ELEV = 1,      /* ghost imposes zeta = A sin(2 pi t / T + phase),     */
+                            /* extrapolates q, takes c_in on inflow                */
+       SW_BC_OPEN = 2,      /* ghost copies the interior state                     */
+       SW_BC_PERIODIC = 3 };/* opposite sides are joined (must come in pairs)      */
+
+enum { SW_RULE_EQ = 0,      /* closed equispaced (composite trapezoid) rule         */
+       SW_RULE_GLL = 1 };   /* Gauss-Legendre-Lobatto rule                         */
+
+enum { SW_RK_FE = 0, SW_RK_SSP3 = 1, SW_RK_RK32 = 2, SW_RK_RK44 = 3 };  /* Appendix A */
+
+typedef struct {
+  int32_t nx0, ny0;          /* coarse grid, cells of size dx0                     */
+  double x0, y0, dx0;        /* lower-left corner and coarse cell size             */
+  int32_t n_cells;           /* number of quadtree leaves                          */
+  const int32_t *level;      /* host [n_cells]: leaf level L, cell size dx0/2^L    */
+  const int32_t *i, *j;      /* host [n_cells]: position in level-L units          */
+  int32_t bc[4];             /* west, east, south, north: SW_BC_*                  */
+} sw_mesh_desc;
+
+typedef struct {
+  int32_t r;                 /* polynomial degree 1..3                             */
+  int32_t rule;              /* SW_RULE_*                                          */
+  int32_t n_levels;          /* entries used in S                                  */
+  int32_t S[8];              /* sample nodes per direction per level, r+2 <= S <= 32 */
+  int32_t rk;                /* SW_RK_*                                            */
+  double g;                  /* gravity                                            */
+  double eps;                /* velocity desingularisation depth (eq:velocity) > 0 */
+  double h_lim;              /* degree-coarsening depth (eq:criteria_p)            */
+  double eps0;               /* dry-cell lift of the Newton guess (eq:initial_guess)*/
+  int32_t newton_max;        /* Newton iteration cap                               */
+  double cfl;                /* dt = cfl * min over face nodes of w J_K/(lambda l) */
+  int32_t cfl_mode;          /* 0: w = 1; 1: w = end-point weight of the rule      */
+  int32_t tracer;            /* 0 or 1 passive tracer                              */
+  int32_t adapt_degree;      /* 1: degree coarsening on, 0: always degree r        */
+  double tide_amp, tide_period, tide_phase, tide_c_in;   /* SW_BC_ELEV data         */
+} sw_params;
+
+typedef struct {
+  double total_mass;         /* sum over cells of int max(zeta - b, 0) (eq:positivity-7) */
+  double min_target_mass;    /* min over cells and stages of the element target mass     */
+  double dt;                 /* time step of the last step                              */
+  double t;                  /* model time                                              */
+  int64_t n_pos_viol;        /* (cell, stage) pairs with negative target mass           */
+  int32_t max_newton_it;     /* largest Newton iteration count in the last step          */
+  int32_t nonfinite;         /* 1 if a non-finite value was found in the state           */
+  int64_t n_r0_cells;        /* cells at degree 0 in the last step                       */
+  int64_t n_fallback;        /* masked Jacobians replaced by the constant-mode update    */
+  int64_t step;              /* steps taken                                              */
+} sw_diag;
+
+/* Create a context: validates the mesh (leaves tile the domain, 2:1 balance,
+ * level order) and parameters, builds faces and reference tables, allocates
+ * device memory.  `stream` is a hipStream_t (NULL: the default stream).
+ * Errors: SW_EINVAL (bad mesh/params), SW_ENOMEM, SW_EHIP. */
+sw_status sw_create(sw_ctx **out, const sw_mesh_desc *mesh, const sw_params *p, void *stream);
+void sw_destroy(sw_ctx *c);
+const char *sw_last_error(void);
+
+/* Sizes: cells, sample nodes (sum of S_L^2), nodal values per field. */
+sw_status sw_counts(const sw_ctx *c, int64_t *n_cells, int64_t *n_vol_nodes, int64_t *n_dofs);
+
+/* Host outputs: sample-node coordinates [n_vol_nodes][2] and basis support
+ * point coordinates [n_dofs][2].  Synchronises. */
+sw_status sw_node_coords(const sw_ctx *c, double *xy_host);
+sw_status sw_dof_coords(const sw_ctx *c, double *xy_host);
+
+/* Bed ELEVATION b at the sample nodes (device, [n_vol_nodes]).  The library
+ * stores the bathymetry depth z_b = -(b + db_K) of Sec. 2 (db: bed offset). */
+sw_status sw_set_bathymetry(sw_ctx *c, const double *b_dev);
+/* Per-cell Manning coefficient n_K (eq:manning), device [n_cells]. */
+sw_status sw_set_manning(sw_ctx *c, const double *n_dev);
+/* Per-cell bed-elevation offset db_K added to every sample of cell K, device [n_cells]. */
+sw_status sw_set_bed_offset(sw_ctx *c, const double *db_dev);
+
+/* State I/O, device [n_dofs] each; tracer may be NULL (then zero / not copied).
+ * sw_set_state also resets every cell to degree r. */
+sw_status sw_set_state(sw_ctx *c, const double *eta, const double *qx, const double *qy, const double *tracer);
+sw_status sw_get_state(const sw_ctx *c, double *eta, double *qx, double *qy, double *tracer);
+/* Definition 3.1: zeta_j = eta_j in cells with a wet sample node
+ * (eta(x_q) - b(x_q) > 0), zeta_j = min_q b(x_q) elsewhere; q = 0. */
+sw_status sw_init_lake_at_rest(sw_ctx *c, const double *eta_dev);
+sw_status sw_set_time(sw_ctx *c, double t);
+
+/* Weak residuals of the degree-r test functions for the given state (device
+ * inputs/outputs, [n_dofs] each; tracer/R may be NULL): F (eq:mass_rhs),
+ * Gx, Gy (eq:discharge_rhs with the friction term of eq:discharge_rhs_implicit
+ * added explicitly), R (eq:r_concentration).  dtb_dev (device double, may be
+ * NULL) receives min over face nodes/sides of w J_K/(lambda l) (Prop. 3.2). */
+sw_status sw_apply_operator(sw_ctx *c, const double *eta, const double *qx, const double *qy,
+                            const double *tracer, double t, double *F, double *Gx, double *Gy,
+                            double *R, double *dtb_dev);
+
+/* One RK step split in its parts (Sec. 3.1, Butcher form):
+ *   sw_step_begin: degree adaptation + conservative remap, H(zeta^n), C~^n,
+ *                  stage-1 residuals; dt = given dt if dt > 0, else from the
+ *                  CFL reduction of the stage-1 fluxes (kept on the device);
+ *   sw_rk_stage(l), l = 2..s: stage-l state from the stored residuals
+ *                  (Newton, discharge and tracer solves) and its residuals;
+ *   sw_step_end:   final combination with the weights b and the solves.
+ * sw_step runs the three; sw_run runs n steps. */
+sw_status sw_step_begin(sw_ctx *c, double dt);
+sw_status sw_rk_stage(sw_ctx *c, int32_t l);
+sw_status sw_step_end(sw_ctx *c);
+sw_status sw_step(sw_ctx *c, double dt);
+sw_status sw_run(sw_ctx *c, int32_t n_steps, double dt);
+
+/* Diagnostics of the last step (host output).  Synchronises. */
+sw_status sw_diagnostics(const sw_ctx *c, sw_diag *out_host);
+/* Wait for the context's stream; reports SW_EDEVICE if a kernel flagged an error. */
+sw_status sw_sync(sw_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H_ */

@@ -1,0 +1,257 @@
+"""Thin ctypes binding of include/sw.h (argument marshalling only).
+
+Device buffers are torch CUDA tensors; every step of the method runs in the
+HIP library.  Loading fails loudly if libswdg.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libswdg.so")
+
+BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3}
+RULE = {"eq": 0, "gll": 1}
+RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3}
+
+EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_counts", "sw_node_coords", "sw_dof_coords",
+           "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset", "sw_set_state", "sw_get_state",
+           "sw_init_lake_at_rest", "sw_set_time", "sw_apply_operator", "sw_step_begin", "sw_rk_stage",
+           "sw_step_end", "sw_step", "sw_run", "sw_diagnostics", "sw_sync"]
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_dp = ctypes.c_void_p
+
+
+class SwMeshDesc(ctypes.Structure):
+    _fields_ = [("nx0", ctypes.c_int32), ("ny0", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("dx0", ctypes.c_double), ("n_cells", ctypes.c_int32),
+                ("level", _c_i32p), ("i", _c_i32p), ("j", _c_i32p), ("bc", ctypes.c_int32 * 4)]
+
+
+class SwParams(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("rule", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("S", ctypes.c_int32 * 8), ("rk", ctypes.c_int32), ("g", ctypes.c_double),
+                ("eps", ctypes.c_double), ("h_lim", ctypes.c_double), ("eps0", ctypes.c_double),
+                ("newton_max", ctypes.c_int32), ("cfl", ctypes.c_double), ("cfl_mode", ctypes.c_int32),
+                ("tracer", ctypes.c_int32), ("adapt_degree", ctypes.c_int32), ("tide_amp", ctypes.c_double),
+                ("tide_period", ctypes.c_double), ("tide_phase", ctypes.c_double), ("tide_c_in", ctypes.c_double)]
+
+
+class SwDiag(ctypes.Structure):
+    _fields_ = [("total_mass", ctypes.c_double), ("min_target_mass", ctypes.c_double), ("dt", ctypes.c_double),
+                ("t", ctypes.c_double), ("n_pos_viol", ctypes.c_int64), ("max_newton_it", ctypes.c_int32),
+                ("nonfinite", ctypes.c_int32), ("n_r0_cells", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("step", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def load():
+    """Load libswdg.so (raises if it is missing: there is no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} not found: build it with paper_2505_18743_amd.build.build_library()")
+    L = ctypes.CDLL(LIBPATH)
+    vp = ctypes.c_void_p
+    L.sw_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SwMeshDesc), ctypes.POINTER(SwParams), vp]
+    L.sw_destroy.argtypes = [vp]
+    L.sw_destroy.restype = None
+    L.sw_last_error.restype = ctypes.c_char_p
+    L.sw_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int64)]
+    L.sw_node_coords.argtypes = [vp, vp]
+    L.sw_dof_coords.argtypes = [vp, vp]
+    L.sw_set_bathymetry.argtypes = [vp, vp]
+    L.sw_set_manning.argtypes = [vp, vp]
+    L.sw_set_bed_offset.argtypes = [vp, vp]
+    L.sw_set_state.argtypes = [vp, vp, vp, vp, vp]
+    L.sw_get_state.argtypes = [vp, vp, vp, vp, vp]
+    L.sw_init_lake_at_rest.argtypes = [vp, vp]
+    L.sw_set_time.argtypes = [vp, ctypes.c_double]
+    L.sw_apply_operator.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
+    L.sw_step_begin.argtypes = [vp, ctypes.c_double]
+    L.sw_rk_stage.argtypes = [vp, ctypes.c_int32]
+    L.sw_step_end.argtypes = [vp]
+    L.sw_step.argtypes = [vp, ctypes.c_double]
+    L.sw_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
+    L.sw_diagnostics.argtypes = [vp, ctypes.POINTER(SwDiag)]
+    L.sw_sync.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("sw_destroy", "sw_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+def _check(st, what):
+    if st != 0:
+        msg = load().sw_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed with status {st}: {msg}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def make_params(pd):
+    p = SwParams()
+    p.r = int(pd["r"])
+    p.rule = RULE[pd.get("rule", "eq")]
+    S = list(pd["S"])
+    p.n_levels = len(S)
+    for k, s in enumerate(S):
+        p.S[k] = int(s)
+    p.rk = RK[pd.get("rk", "ssp3")]
+    p.g = float(pd.get("g", 9.81))
+    p.eps = float(pd.get("eps", 0.1))
+    p.h_lim = float(pd.get("h_lim", 0.1))
+    p.eps0 = float(pd.get("eps0", 1e-8))
+    p.newton_max = int(pd.get("newton_max", 20))
+    p.cfl = float(pd.get("cfl", 0.2))
+    p.cfl_mode = int(pd.get("cfl_mode", 0))
+    p.tracer = int(bool(pd.get("tracer", False)))
+    p.adapt_degree = int(bool(pd.get("adapt_degree", True)))
+    tide = tuple(pd.get("tide", (0.0, 1.0, 0.0, 0.0)))
+    p.tide_amp, p.tide_period, p.tide_phase, p.tide_c_in = (float(v) for v in tide)
+    return p
+
+
+class Solver:
+    """One context of the HIP library on one device and stream."""
+
+    def __init__(self, mesh, params, device="cuda:0"):
+        L = load()
+        self.dev = torch.device(device)
+        self.params = dict(params)
+        self._lev = np.ascontiguousarray(mesh["level"], dtype=np.int32)
+        self._i = np.ascontiguousarray(mesh["i"], dtype=np.int32)
+        self._j = np.ascontiguousarray(mesh["j"], dtype=np.int32)
+        d = SwMeshDesc()
+        d.nx0, d.ny0 = int(mesh["nx0"]), int(mesh["ny0"])
+        d.x0, d.y0, d.dx0 = float(mesh["x0"]), float(mesh["y0"]), float(mesh["dx0"])
+        d.n_cells = len(self._lev)
+        d.level = self._lev.ctypes.data_as(_c_i32p)
+        d.i = self._i.ctypes.data_as(_c_i32p)
+        d.j = self._j.ctypes.data_as(_c_i32p)
+        for k, b in enumerate(mesh["bc"]):
+            d.bc[k] = BC[b]
+        p = make_params(params)
+        with torch.cuda.device(self.dev):
+            self.stream = torch.cuda.current_stream(self.dev)
+            h = ctypes.c_void_p()
+            _check(L.sw_create(ctypes.byref(h), ctypes.byref(d), ctypes.byref(p),
+                               ctypes.c_void_p(self.stream.cuda_stream)), "sw_create")
+        self.h = h
+        nc, nv, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.sw_counts(self.h, ctypes.byref(nc), ctypes.byref(nv), ctypes.byref(nd)), "sw_counts")
+        self.n_cells, self.n_vol, self.n_dofs = nc.value, nv.value, nd.value
+        self.np_ = self.n_dofs // self.n_cells
+        self.tracer = bool(params.get("tracer", False))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers ----
+    def _dev(self, a, n=None):
+        t = torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a, dtype=torch.float64)
+        t = t.to(self.dev).contiguous().reshape(-1)
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def zeros(self):
+        return torch.zeros(self.n_dofs, dtype=torch.float64, device=self.dev)
+
+    # ---- setup ----
+    def node_coords(self):
+        xy = np.zeros((self.n_vol, 2))
+        _check(load().sw_node_coords(self.h, xy.ctypes.data_as(ctypes.c_void_p)), "sw_node_coords")
+        return xy
+
+    def dof_coords(self):
+        xy = np.zeros((self.n_dofs, 2))
+        _check(load().sw_dof_coords(self.h, xy.ctypes.data_as(ctypes.c_void_p)), "sw_dof_coords")
+        return xy
+
+    def set_bathymetry(self, b):
+        t = self._dev(b, self.n_vol)
+        _check(load().sw_set_bathymetry(self.h, _ptr(t)), "sw_set_bathymetry")
+        self._keep = t
+
+    def set_manning(self, n):
+        t = self._dev(n, self.n_cells)
+        _check(load().sw_set_manning(self.h, _ptr(t)), "sw_set_manning")
+        self._keep_n = t
+
+    def set_bed_offset(self, db):
+        t = self._dev(db, self.n_cells)
+        _check(load().sw_set_bed_offset(self.h, _ptr(t)), "sw_set_bed_offset")
+        self._keep_db = t
+
+    def set_state(self, eta, qx, qy, c=None):
+        ts = [self._dev(a, self.n_dofs) for a in (eta, qx, qy)]
+        tc = self._dev(c, self.n_dofs) if c is not None else None
+        _check(load().sw_set_state(self.h, *[_ptr(t) for t in ts], _ptr(tc)), "sw_set_state")
+        self._keep_s = (ts, tc)
+
+    def get_state(self):
+        out = [self.zeros() for _ in range(4)]
+        _check(load().sw_get_state(self.h, *[_ptr(t) for t in out]), "sw_get_state")
+        return out
+
+    def init_lake_at_rest(self, eta):
+        t = self._dev(eta, self.n_dofs)
+        _check(load().sw_init_lake_at_rest(self.h, _ptr(t)), "sw_init_lake_at_rest")
+        self._keep_l = t
+
+    def set_time(self, t):
+        _check(load().sw_set_time(self.h, float(t)), "sw_set_time")
+
+    # ---- operator and stepping ----
+    def apply_operator(self, eta, qx, qy, c=None, t=0.0):
+        ins = [self._dev(a, self.n_dofs) for a in (eta, qx, qy)]
+        tc = self._dev(c, self.n_dofs) if c is not None else self.zeros()
+        outs = [self.zeros() for _ in range(4)]
+        dtb = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        _check(load().sw_apply_operator(self.h, *[_ptr(x) for x in ins], _ptr(tc), float(t),
+                                        *[_ptr(x) for x in outs], _ptr(dtb)), "sw_apply_operator")
+        return outs[0], outs[1], outs[2], outs[3], dtb
+
+    def step_begin(self, dt=0.0):
+        _check(load().sw_step_begin(self.h, float(dt)), "sw_step_begin")
+
+    def rk_stage(self, l):
+        _check(load().sw_rk_stage(self.h, int(l)), "sw_rk_stage")
+
+    def step_end(self):
+        _check(load().sw_step_end(self.h), "sw_step_end")
+
+    def step(self, dt=0.0):
+        _check(load().sw_step(self.h, float(dt)), "sw_step")
+
+    def run(self, n, dt=0.0):
+        _check(load().sw_run(self.h, int(n), float(dt)), "sw_run")
+
+    def sync(self):
+        _check(load().sw_sync(self.h), "sw_sync")
+
+    def diagnostics(self):
+        d = SwDiag()
+        _check(load().sw_diagnostics(self.h, ctypes.byref(d)), "sw_diagnostics")
+        return {k: getattr(d, k) for k, _ in SwDiag._fields_}

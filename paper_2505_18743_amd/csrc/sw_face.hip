@@ -1,0 +1,157 @@
+// Face kernel of the sub-grid DG shallow-water operator (gfx950, FP64).
+//
+// One face per group of P = pow2 >= S lanes, lane alpha owning face node
+// alpha of the fine (or equal) side's closed S-point rule, whose nodes are the
+// boundary row of that side's sample grid.  Each lane reconstructs both traces
+// from the (r+1) nodal coefficients of the face row (GLL support points include
+// the element end points, so the trace depends on that row only), applies
+// hydrostatic reconstruction (eq:hydro_rec, eq:hydro_rec_vars) and the Rusanov
+// flux (eq:lxf_parameter), and the projections onto the (r+1) face test
+// functions of each side are finished by a butterfly over the face's lanes.
+// The result goes to a per-face buffer that the element kernel of the next
+// stage gathers in a fixed order (no floating-point atomics).
+#include "sw_dev.h"
+
+namespace swk {
+
+template <int R>
+__device__ __forceinline__ int row_dof(int side, int k) {
+  constexpr int N1 = R + 1;
+  return side == 0 ? k * N1 : side == 1 ? k * N1 + R : side == 2 ? k : R * N1 + k;
+}
+
+template <int R, int P>
+__global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
+  constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / P;
+  const int S = A.S;
+  const int tid = threadIdx.x, lane = tid % P, lf = tid / P;
+  const int fl = blockIdx.x * FPB + lf;
+  const bool fv = fl < A.nface;
+  const int flc = fv ? fl : 0;
+  const int f = A.face0 + flc;
+  const bool node = fv && lane < S;
+  const int al = node ? lane : 0;
+  int cA = A.fA[f], cB = A.fB[f];
+  const int meta = A.meta[f];
+  const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
+  const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 3;
+  const bool ok = (cA >= 0 && cA < A.K) && (bnd || (cB >= 0 && cB < A.K));
+  if (!ok && node) atomicOr(A.err, 2);
+  const bool act = node && ok;
+  if (!ok) cA = cB = 0;
+  if (bnd) cB = cA;
+
+  double la[N1], lb[N1];
+  const double* tA = A.fl + (size_t)al * N1;
+  const double* tB = A.fl + ((size_t)(sub < 0 ? 0 : 1 + sub) * S + al) * N1;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    la[k] = tA[k];
+    lb[k] = tB[k];
+  }
+  double vA[4], vB[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double sa = 0.0, sb = 0.0;
+    if (q < 3 || A.tracer) {
+      const double* sp = A.st[q];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        sa += la[k] * sp[(size_t)cA * NP + row_dof<R>(sA, k)];
+        sb += lb[k] * sp[(size_t)cB * NP + row_dof<R>(sB, k)];
+      }
+    }
+    vA[q] = sa;
+    vB[q] = sb;
+  }
+  const double nx = sA == 0 ? -1.0 : (sA == 1 ? 1.0 : 0.0);
+  const double ny = sA == 2 ? -1.0 : (sA == 3 ? 1.0 : 0.0);
+  const double zA = A.zf[((size_t)flc * 2 + 0) * S + al];
+  double zB = A.zf[((size_t)flc * 2 + 1) * S + al];
+  if (bnd) {
+    zB = zA;
+    if (bc == 0) {            // wall: mirror the normal discharge
+      const double qn = vA[1] * nx + vA[2] * ny;
+      vB[0] = vA[0];
+      vB[1] = vA[1] - 2.0 * qn * nx;
+      vB[2] = vA[2] - 2.0 * qn * ny;
+      vB[3] = vA[3];
+    } else if (bc == 1) {     // imposed elevation (tide), q extrapolated
+      const double tt = A.scal[1] + A.cstage * A.scal[0];
+      vB[0] = A.tide_amp * sin(6.283185307179586 * tt / A.tide_period + A.tide_phase);
+      vB[1] = vA[1];
+      vB[2] = vA[2];
+      vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? A.tide_cin : vA[3];
+    } else {                  // open: copy
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vB[q] = vA[q];
+    }
+  }
+  const double g = A.g, eps = A.eps;
+  const double sAw = vA[0] + zA, sBw = vB[0] + zB;
+  const double hA = sAw > 0.0 ? sAw : 0.0, hB = sBw > 0.0 ? sBw : 0.0;
+  const double ihA = inv_des(hA, eps), ihB = inv_des(hB, eps);
+  const double uxA = vA[1] * ihA, uyA = vA[2] * ihA, uxB = vB[1] * ihB, uyB = vB[2] * ihB;
+  const double unA = uxA * nx + uyA * ny, unB = uxB * nx + uyB * ny;
+  const double lA = fabs(unA) + sqrt(g * hA), lB = fabs(unB) + sqrt(g * hB);
+  const double lam = lA >= lB ? lA : lB;
+  const double zs = zA <= zB ? zA : zB;                       // z*_b = min(zb-, zb+)
+  const double tsA = vA[0] + zs, tsB = vB[0] + zs;
+  const double hsA = tsA > 0.0 ? tsA : 0.0, hsB = tsB > 0.0 ? tsB : 0.0;
+  const double qsxA = hsA * uxA, qsyA = hsA * uyA, qsxB = hsB * uxB, qsyB = hsB * uyB;
+  const double esA = vA[0] >= -zs ? vA[0] : -zs, esB = vB[0] >= -zs ? vB[0] : -zs;
+  const double mass = 0.5 * ((qsxA + qsxB) * nx + (qsyA + qsyB) * ny) + 0.5 * lam * (esA - esB);
+  const double momx = 0.5 * (qsxA * unA + qsxB * unB) + 0.5 * lam * (qsxA - qsxB);
+  const double momy = 0.5 * (qsyA * unA + qsyB * unB) + 0.5 * lam * (qsyA - qsyB);
+  const double pres = 0.5 * g * 0.5 * (hsA + hsB) * (esA - esB);
+  const double trac = 0.5 * ((qsxA * vA[3] + qsxB * vB[3]) * nx + (qsyA * vA[3] + qsyB * vB[3]) * ny) +
+                      0.5 * lam * (hsA * vA[3] - hsB * vB[3]);
+  const double dxA = A.cdx[cA];
+  const double wl = act ? A.w[al] * dxA : 0.0;
+  const double cAv[4] = {-mass, -momx + pres * nx, -momy + pres * ny, -trac};
+  const double cBv[4] = {mass, momx + pres * nx, momy + pres * ny, trac};
+  double* out = A.fbuf + (size_t)f * 8 * N1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const double va = gsum<P>(wl * cAv[q] * la[k]);
+      const double vb = gsum<P>(bnd ? 0.0 : wl * cBv[q] * lb[k]);
+      const int ia = q * N1 + k, ib = 4 * N1 + q * N1 + k;
+      if (fv && ok && (ia % P) == lane) out[ia] = va;
+      if (fv && ok && (ib % P) == lane) out[ib] = vb;
+    }
+  }
+  // positivity time-step bound (Prop. 3.2): w J_K / (lambda l_Gamma) on both sides
+  double bnd_dt = 1e300;
+  if (act && lam > 0.0) {
+    bnd_dt = A.cw1[cA] * A.cdx[cA] * A.cdx[cA] / (lam * dxA);
+    if (!bnd) bnd_dt = fmin(bnd_dt, A.cw1[cB] * A.cdx[cB] * A.cdx[cB] / (lam * dxA));
+  }
+  bnd_dt = gmin<kWave>(bnd_dt);
+  if (tid == 0) A.bpart[A.bpart0 + blockIdx.x] = bnd_dt;
+}
+
+template <int R>
+static hipError_t face_r(int P, const FaceArgs& a, int nblk, hipStream_t s) {
+  switch (P) {
+    case 4: hipLaunchKernelGGL((k_face<R, 4>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_face<R, 8>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_face<R, 16>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_face<R, 32>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return face_r<1>(P, a, nblk, s);
+    case 2: return face_r<2>(P, a, nblk, s);
+    case 3: return face_r<3>(P, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace swk

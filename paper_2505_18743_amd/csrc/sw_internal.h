@@ -1,0 +1,100 @@
+// Internal declarations shared by the host side and the gfx950 kernels of the
+// sub-grid DG shallow-water library (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swk {
+
+constexpr int kWave = 64;
+
+// ---- stage-kernel modes ---------------------------------------------------
+enum Mode : int {
+  M_APPLY = 0,  // volume residual of a given state
+  M_FOLD = 1,   // residual slot + face contributions -> output arrays
+  M_START = 2,  // degree adaptation, remap, H^n, C~^n, stage-1 volume residual
+  M_STAGE = 3,  // stage-l solves from stored residuals + volume residual
+  M_FINAL = 4,  // final combination + solves + mass diagnostics
+  M_TRACER = 5  // tracer-only replay of a stored stage
+};
+
+// per-level reference tables on the device
+struct LevelTabs {
+  const double* w;      // [S]          1-D rule weights on [0,1]
+  const double* l;      // [S][N1]      l_k(xhat_a)
+  const double* d;      // [S][N1]      l_k'(xhat_a)
+  const double* m0inv;  // [NP][NP]     inverse all-wet rule mass matrix, unit square
+  const double* mqinv;  // [NP][NP]     inverse exact mass matrix, unit square
+  const double* meanw;  // [NP]         int psi_j over the unit square
+  const double* fl;     // [3][S][N1]   l_k at face nodes: s, s/2, (1+s)/2
+  int S;
+  double dx;
+};
+
+// diagnostics partial slots per stage-kernel block
+enum { D_MINT = 0, D_VIOL, D_NEWT, D_FALLB, D_MASS, D_NR0, D_NONF, D_NSLOT };
+
+struct StageArgs {
+  LevelTabs t;
+  int cell0, ncell, K;
+  const double* zb;      // level block of internal depth samples [ncell][S(a)][S(b)]
+  const double* bvec;    // [K][NP] all-wet B_i = sum W psi_i zb
+  const double* zmax;    // [K]     max depth sample
+  const double* nman;    // [K]
+  double* sn[4];         // persistent state (zeta, qx, qy, c) [K][NP]
+  double* ss[4];         // stage state
+  const double* in[4];   // M_APPLY / M_TRACER inputs
+  double* out[4];        // M_FOLD outputs
+  double* hn;            // [K][NP] H(zeta^n)
+  double* cn;            // [K][NP] C~^n
+  double* res;           // [NS][4][K][NP]
+  const double* fbuf;    // [F][2][4][N1]
+  const int* cface;      // [K][8]
+  int nface2;            // 2 * number of faces (bound of cface entries)
+  int8_t* flag;          // [K] current degree (r or 0)
+  int8_t* allwet;        // [K] zeta^n wet at every sample node
+  const double* scal;    // device scalars: [0] dt, [1] t
+  double* dpart;         // [nblk_total][D_NSLOT]
+  int dpart0;            // first block slot of this launch
+  int* err;
+  int slot;              // residual slot written (M_APPLY/M_START/M_STAGE) or folded
+  int fold;              // residual slot to fold (M_STAGE/M_FINAL), -1 none
+  int nterm;             // number of stored residuals combined
+  double a[4];           // combination weights a_{l,m} or b_m
+  double g, eps, hlim, eps0;
+  int newton_max, tracer, fric, adapt;
+};
+
+struct FaceArgs {
+  int face0, nface, K, S;
+  const int* fA;
+  const int* fB;
+  const int* meta;       // sideA | sideB<<2 | (sub+1)<<4 | boundary<<6 | bc<<8
+  const double* zf;      // group block [nface][2][S]
+  const double* st[4];
+  double* fbuf;          // [F][2][4][N1]
+  const double* cdx;     // [K]
+  const double* cw1;     // [K]
+  const double* fl;      // [3][S][N1]
+  const double* w;       // [S]
+  const double* scal;    // [0] dt, [1] t
+  double cstage;         // c_l of the stage
+  double* bpart;         // per-block dt bounds
+  int bpart0;
+  int* err;
+  double g, eps;
+  int tracer;
+  double tide_amp, tide_period, tide_phase, tide_cin;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s);
+
+inline int lanes_for(int S) {
+  int P = 4;
+  while (P < S) P <<= 1;
+  return P;
+}
+
+}  // namespace swk

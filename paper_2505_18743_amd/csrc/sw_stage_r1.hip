@@ -1,0 +1,29 @@
+// Element-kernel instantiations for degree r = 1.
+#include "sw_stage.inc"
+
+namespace swk {
+
+template <int P>
+static hipError_t stage_p(int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (mode) {
+    case M_APPLY: hipLaunchKernelGGL((k_stage<1, P, M_APPLY>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case M_FOLD: hipLaunchKernelGGL((k_stage<1, P, M_FOLD>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case M_START: hipLaunchKernelGGL((k_stage<1, P, M_START>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case M_STAGE: hipLaunchKernelGGL((k_stage<1, P, M_STAGE>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case M_FINAL: hipLaunchKernelGGL((k_stage<1, P, M_FINAL>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (P) {
+    case 4: return stage_p<4>(mode, a, nblk, s);
+    case 8: return stage_p<8>(mode, a, nblk, s);
+    case 16: return stage_p<16>(mode, a, nblk, s);
+    case 32: return stage_p<32>(mode, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace swk

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP library (through the C ABI) against the oracle, element
+by element, on identical seeded inputs.
+
+Tolerances (per field, relative to the oracle's max-norm): 1e-12 for one
+residual evaluation, 1e-10 for the state after 100 steps.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import build_oracle, mesh_from_desc
+from oracle import Mesh, Oracle, Params
+from workloads import quadtree_desc, uniform_mesh_desc, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL_RHS = 1e-12
+TOL_STEP = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(g, r):
+    g = np.asarray(g).ravel()
+    r = np.asarray(r).ravel()
+    scale = np.abs(r).max()
+    return np.abs(g - r).max() / (scale if scale > 0 else 1.0)
+
+
+def solver_for(wl, o, b, **over):
+    from paper_2505_18743_amd import Solver
+    params = dict(wl["params"])
+    params.update(over)
+    s = Solver(wl["mesh"], params, device="cuda:0")
+    s.set_bathymetry(b)
+    s.set_manning(wl["manning"] if "manning" in wl else np.zeros(o.m.K))
+    return s
+
+
+def cpu(t, K):
+    return t.detach().cpu().numpy().reshape(K, -1)
+
+
+def oracle_params(o):
+    p = o.p
+    return dict(r=p.r, S=p.S, rule=p.rule, rk=p.rk, g=p.g, eps=p.eps, h_lim=p.h_lim, eps0=p.eps0,
+                newton_max=p.newton_max, cfl=p.cfl, cfl_mode=p.cfl_mode, tracer=p.tracer, tide=p.tide,
+                adapt_degree=p.adapt_degree)
+
+
+def mesh_dict(m):
+    return dict(nx0=m.nx0, ny0=m.ny0, x0=m.x0, y0=m.y0, dx0=m.dx0, level=m.level, i=m.ii, j=m.jj, bc=m.bc)
+
+
+def gpu_from_oracle(o, b, manning=None):
+    from paper_2505_18743_amd import Solver
+    s = Solver(mesh_dict(o.m), oracle_params(o), device="cuda:0")
+    s.set_bathymetry(b)
+    s.set_manning(manning if manning is not None else o.nman.numpy())
+    return s
+
+
+# ---------------------------------------------------------------------------
+
+def test_coordinates_match_oracle():
+    say("case: coordinates coastal_steps_16")
+    wl = workload("coastal_steps_16")
+    o, b = build_oracle(wl)
+    s = solver_for(wl, o, b)
+    assert np.abs(s.node_coords() - o.node_coords()).max() < 1e-12
+    assert np.abs(s.dof_coords() - o.dof_coords().reshape(-1, 2)).max() < 1e-12
+
+
+def test_apply_operator_coastal_steps():
+    say("case: apply_operator coastal_steps_16")
+    wl = workload("coastal_steps_16")
+    o, b = build_oracle(wl)
+    s = solver_for(wl, o, b)
+    rng = np.random.default_rng(7)
+    st = o.get_state()
+    for trial in range(3):
+        if trial > 0:      # random non-trivial states, including dry nodes
+            st = [st[0] + rng.uniform(-0.3, 0.3, st[0].shape), rng.uniform(-1, 1, st[0].shape),
+                  rng.uniform(-1, 1, st[0].shape), st[3]]
+        F, Gx, Gy, R, dtb = o.apply_operator(st, 0.0)
+        g = s.apply_operator(st[0], st[1], st[2], st[3], 0.0)
+        s.sync()
+        K = o.m.K
+        for name, gg, rr in (("F", g[0], F), ("Gx", g[1], Gx), ("Gy", g[2], Gy)):
+            e = rel(cpu(gg, K), rr)
+            say(f"  trial {trial} {name} rel err {e:.3e}")
+            assert e < TOL_RHS, (trial, name, e)
+        assert float(g[4].cpu()[0]) == pytest.approx(dtb, rel=1e-12)
+
+
+def hanging_case(r=2, S=(16, 8), tracer=True, bc=("elev", "wall", "wall", "open")):
+    def refine(L, cand):
+        return [c for c in cand if (c[1] * 5 + c[2] * 3) % 4 == 0]
+    d = quadtree_desc(6, 5, 0.0, 0.0, 400.0, refine, len(S) - 1, bc=bc)
+    m = mesh_from_desc(d)
+    p = Params(r=r, S=S, rule="eq", rk="ssp3", eps=0.05, h_lim=0.05, cfl=0.5, cfl_mode=1, tracer=tracer,
+               tide=(0.3, 3000.0, 0.2, 0.25))
+    o = Oracle(m, p)
+    xy = o.node_coords()
+    b = -3.0 + 4.5 * xy[:, 0] / 2400.0 + 0.6 * np.sin(xy[:, 1] / 150.0) * np.cos(xy[:, 0] / 90.0)
+    b = np.where(np.abs(xy[:, 1] - 1010.0) < 60.0, b - 1.0, b)
+    o.set_bathymetry(b)
+    o.set_manning(np.full(m.K, 0.03))
+    dof = o.dof_coords()
+    eta = 0.4 * np.exp(-((dof[..., 0] - 700) ** 2 + (dof[..., 1] - 1000) ** 2) / 300.0 ** 2)
+    c0 = np.exp(-((dof[..., 0] - 1200) ** 2 + (dof[..., 1] - 900) ** 2) / 400.0 ** 2)
+    o.init_lake_at_rest(eta)
+    o.state[3] = torch.as_tensor(c0)
+    return o, b
+
+
+@pytest.mark.parametrize("r,S", [(1, (8, 4)), (2, (16, 8)), (3, (16, 8, 5))])
+def test_apply_operator_hanging_tracer(r, S):
+    say(f"case: apply_operator hanging r={r} S={S}")
+    o, b = hanging_case(r, S)
+    assert any(f[4] >= 0 for f in o.m.faces)
+    s = gpu_from_oracle(o, b)
+    rng = np.random.default_rng(11)
+    st = o.get_state()
+    st = [st[0], rng.uniform(-0.5, 0.5, st[0].shape), rng.uniform(-0.5, 0.5, st[0].shape), st[3]]
+    t = 700.0
+    F, Gx, Gy, R, dtb = o.apply_operator(st, t)
+    g = s.apply_operator(st[0], st[1], st[2], st[3], t)
+    s.sync()
+    K = o.m.K
+    for name, gg, rr in (("F", g[0], F), ("Gx", g[1], Gx), ("Gy", g[2], Gy), ("R", g[3], R)):
+        e = rel(cpu(gg, K), rr)
+        say(f"  {name} rel err {e:.3e}")
+        assert e < TOL_RHS, (name, e)
+
+
+def compare_states(o, s, tol, label):
+    K = o.m.K
+    got = [cpu(t, K) for t in s.get_state()]
+    ref = o.get_state()
+    names = ("eta", "qx", "qy", "c")
+    for q in range(4 if o.p.tracer else 3):
+        e = rel(got[q], ref[q])
+        say(f"  {label} {names[q]} rel err {e:.3e}")
+        assert e < tol, (label, names[q], e)
+
+
+def run_both(o, s, nsteps, dt=None, check_every=None):
+    dmax = 0
+    for n in range(nsteps):
+        d = o.step(dt)
+        s.step(dt if dt else 0.0)
+        if check_every and (n + 1) % check_every == 0:
+            s.sync()
+    s.sync()
+    return d
+
+
+def test_steps_coastal_steps_full_workload():
+    """The 16x16 coastal workload for all its 100 SSP3 steps, CFL-controlled dt."""
+    say("case: 100 steps coastal_steps_16")
+    wl = workload("coastal_steps_16")
+    o, b = build_oracle(wl)
+    s = solver_for(wl, o, b)
+    s.set_state(*o.get_state())
+    m0 = o.total_mass()
+    d = run_both(o, s, 100)
+    dg = s.diagnostics()
+    say(f"  oracle dt {d['dt']:.6e} gpu dt {dg['dt']:.6e}, r0 {d['n_r0']} / {dg['n_r0_cells']}")
+    compare_states(o, s, TOL_STEP, "100 steps")
+    assert dg["dt"] == pytest.approx(d["dt"], rel=1e-10)
+    assert dg["t"] == pytest.approx(o.t, rel=1e-10)
+    assert dg["total_mass"] == pytest.approx(m0, rel=1e-12)
+    assert dg["n_r0_cells"] == d["n_r0"]
+
+
+def beach_crop(i0, j0, nx=24, ny=12, surge=None):
+    wl = workload("beach_dambreak_256", window=(i0, j0, nx, ny))
+    if surge is not None:         # a surge running up the dry beach
+        x_front, level = surge
+        wl["eta0"] = lambda x, y: np.where(np.asarray(x) < x_front, level, 0.0)
+    return wl
+
+
+@pytest.mark.parametrize("crop", ["dam", "shore"])
+def test_steps_beach_dambreak_crop(crop):
+    """Windows of the 256x256 case (same cell size, bed, r=2, 16x16 samples):
+    the dam line, and the shoreline with a surge flooding dry cells."""
+    say(f"case: 100 steps beach crop {crop} 24x12")
+    wl = beach_crop(116, 40) if crop == "dam" else beach_crop(200, 60, surge=(16200.0, 0.6))
+    o, b = build_oracle(wl)
+    s = solver_for(wl, o, b)
+    s.set_state(*o.get_state())
+    d = run_both(o, s, 100)
+    dg = s.diagnostics()
+    say(f"  oracle newton {d['newton_it']} gpu {dg['max_newton_it']}; r0 {d['n_r0']} {dg['n_r0_cells']}")
+    compare_states(o, s, TOL_STEP, "100 steps")
+
+
+@pytest.mark.parametrize("rk", ["ssp3", "rk32", "rk44", "fe"])
+def test_steps_hanging_tracer_elev(rk):
+    say(f"case: 20 steps hanging mesh + tracer + tide, {rk}")
+    o, b = hanging_case(2, (16, 8))
+    o.p.rk = rk
+    if rk == "fe":
+        o.p.cfl = 0.5
+    s = gpu_from_oracle(o, b)
+    s.set_state(*o.get_state())
+    run_both(o, s, 20)
+    compare_states(o, s, TOL_STEP, "20 steps")
+
+
+def test_stage_by_stage_matches_step():
+    say("case: step split into begin / rk_stage / end")
+    wl = workload("coastal_steps_16")
+    o, b = build_oracle(wl)
+    s1 = solver_for(wl, o, b)
+    s2 = solver_for(wl, o, b)
+    st = o.get_state()
+    s1.set_state(*st)
+    s2.set_state(*st)
+    for _ in range(3):
+        s1.step()
+        s2.step_begin()
+        s2.rk_stage(2)
+        s2.rk_stage(3)
+        s2.step_end()
+    s1.sync()
+    s2.sync()
+    for a, c in zip(s1.get_state(), s2.get_state()):
+        assert torch.equal(a, c)
+
+
+def test_lake_at_rest_init_matches_oracle():
+    say("case: Definition 3.1 initialisation")
+    wl = workload("coastal_steps_16")
+    o, b = build_oracle(wl)
+    s = solver_for(wl, o, b)
+    dof = o.dof_coords()
+    eta = wl["eta0"](dof[..., 0], dof[..., 1])
+    s.init_lake_at_rest(eta)
+    s.sync()
+    K = o.m.K
+    assert rel(cpu(s.get_state()[0], K), o.get_state()[0]) < 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_edge_single_and_ragged_meshes(n):
+    """1x1, 3x3, 5x5 meshes (cell counts not multiples of the cells per block), S=3 and S=5."""
+    say(f"case: ragged {n}x{n}")
+    m = Mesh.uniform(n, n, 0.0, 0.0, 10.0)
+    for (r, S) in ((1, 3), (2, 5)):
+        p = Params(r=r, S=(S,), rule="gll", rk="ssp3", eps=1e-3, h_lim=1e-3, cfl=0.2)
+        o = Oracle(m, p)
+        xy = o.node_coords()
+        b = -1.0 - 0.2 * np.sin(xy[:, 0] / 7.0) * np.cos(xy[:, 1] / 5.0)
+        o.set_bathymetry(b)
+        rng = np.random.default_rng(n + r)
+        K, npn = m.K, (r + 1) ** 2
+        st = [rng.uniform(-0.1, 0.1, (K, npn)), rng.uniform(-0.2, 0.2, (K, npn)), rng.uniform(-0.2, 0.2, (K, npn))]
+        o.set_state(*st)
+        s = gpu_from_oracle(o, b)
+        F, Gx, Gy, R, dtb = o.apply_operator()
+        g = s.apply_operator(*st, None, 0.0)
+        s.sync()
+        for name, gg, rr in (("F", g[0], F), ("Gx", g[1], Gx), ("Gy", g[2], Gy)):
+            assert rel(cpu(gg, K), rr) < TOL_RHS, (n, r, name)
+        s.set_state(*st)
+        run_both(o, s, 5)
+        compare_states(o, s, TOL_STEP, f"{n}x{n} r={r}")
+
+
+def test_full_size_beach_sampled_residuals():
+    """256x256, r=2, 16x16 samples, as the benchmark launches it: the residual of
+    64 sampled cells against the oracle on the 3x3 patch around each."""
+    say("case: full-size beach_dambreak_256 sampled residuals")
+    wl = workload("beach_dambreak_256")
+    from paper_2505_18743_amd import Solver
+    s = Solver(wl["mesh"], wl["params"], device="cuda:0")
+    xy = s.node_coords()
+    b = wl["bed"](xy[:, 0], xy[:, 1])
+    s.set_bathymetry(b)
+    s.set_manning(wl["manning"])
+    dof = s.dof_coords()
+    eta0 = wl["eta0"](dof[:, 0], dof[:, 1])
+    s.init_lake_at_rest(eta0)
+    s.run(10)
+    st = [t.clone() for t in s.get_state()]
+    g = s.apply_operator(st[0], st[1], st[2], None, 0.0)
+    s.sync()
+    n = 256
+    npn = 9
+    S = 16
+    stn = [t.cpu().numpy().reshape(n, n, npn) for t in st[:3]]
+    res = [t.cpu().numpy().reshape(n, n, npn) for t in g[:3]]
+    bb = b.reshape(n, n, S * S)
+    rng = np.random.default_rng(5)
+    picks = [(int(rng.integers(1, n - 1)), int(rng.integers(1, n - 1))) for _ in range(56)]
+    picks += [(j, 128) for j in (40, 90, 150, 200)] + [(70, 213), (71, 213), (140, 214), (141, 214)]
+    scales = [max(np.abs(r_).max(), 1e-300) for r_ in res]   # full-field max-norms
+    worst = 0.0
+    for (j, i) in picks:
+        m = Mesh.uniform(3, 3, (i - 1) * 78.125, (j - 1) * 78.125, 78.125)
+        o = Oracle(m, Params(**{k: (tuple(v) if k in ("S", "tide") else v) for k, v in wl["params"].items()}))
+        blk = bb[j - 1:j + 2, i - 1:i + 2].reshape(9, S * S)
+        o.set_bathymetry(blk.ravel())
+        o.set_manning(np.full(9, 0.025))
+        patch = [a[j - 1:j + 2, i - 1:i + 2].reshape(9, npn) for a in stn]
+        F, Gx, Gy, R, _ = o.apply_operator(patch + [np.zeros((9, npn))], 0.0)
+        for gg, rr, scale in zip(res, (F, Gx, Gy), scales):
+            worst = max(worst, np.abs(gg[j, i] - rr[4]).max() / scale)
+    say(f"  worst sampled rel err {worst:.3e}")
+    assert worst < TOL_RHS
