@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the sub-grid DG shallow-water step on one MI355X.
+
+Metric: FP64 DoF-updates per second per RK stage (stored nodal values of
+zeta, qx, qy (and c with a tracer) times the stages taken, over the timed
+wall time), on the 256x256, r = 2, 16x16-sample beach dam break (SSP3), with
+every input resident in device memory before the timed region.
+
+One JSON line is printed.  Besides the metric it carries
+  roofline:     the dominant kernel's algorithmic bytes and flops per launch
+                divided by its average launch time (HIP events recorded by
+                the library around its launches, on its stream, during the
+                timed region) against the MI355X peaks;
+  cpu_baseline: the oracle timed on the host cores on a bounded window of
+                the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (and matrix) peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "element_stage_beach_dambreak_256.traffic.json")
+STAGE_SOURCES = ["sw_stage.inc", "sw_dev.h", "sw_internal.h", "sw_stage_r2.hip"]
+
+
+def stage_source_sha():
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_18743_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def element_stage_work(S, r, n_f, stage_terms):
+    """Algorithmic bytes and flops per cell of one launch of the fast element
+    kernel of a stage (Newton first iterate, discharge update, one pass over
+    the samples that verifies the iterate and integrates the volume terms):
+
+    bytes = 8 [ S^2                      bathymetry samples
+              + 3 NP                     zeta^n, q^n
+              + 2 NP                     H(zeta^n), all-wet B
+              + n_f NP m                 m stored stage residuals read
+              + n_f NP                   volume residual written
+              + n_f NP ]                 stage state written
+    flops = S^2 [ 2 (r+1) 5              interpolation of zeta, d_x zeta, d_y zeta, qx, qy
+              + 2 (r+1) 8               8 test-function accumulations (F: 2, Gx: 3, Gy: 3)
+              + 40 ]                     pointwise h, 1/h_des, u, friction, sources, fluxes
+            + 2 NP^2 n_f                M0^{-1} (zeta) and exact-mass inverse (qx, qy)
+    with NP = (r+1)^2 and m the number of stored residuals combined.
+    """
+    NP = (r + 1) ** 2
+    words = S * S + 5 * NP + n_f * NP * (stage_terms + 2)
+    flops = S * S * (2 * (r + 1) * 5 + 2 * (r + 1) * 8 + 40) + 2 * NP * NP * n_f
+    return 8.0 * words, float(flops)
+
+
+def setup(wl, device):
+    import numpy as np
+    from paper_2505_18743_amd import Solver
+    s = Solver(wl["mesh"], wl["params"], device=device)
+    xy = s.node_coords()
+    b = wl["bed"](xy[:, 0], xy[:, 1])
+    s.set_bathymetry(b)
+    s.set_manning(wl["manning"])
+    dof = s.dof_coords()
+    eta0 = wl["eta0"](dof[:, 0], dof[:, 1])
+    c0 = wl["tracer0"](dof[:, 0], dof[:, 1]) if wl.get("tracer0") else None
+
+    def reset():
+        s.init_lake_at_rest(eta0)
+        st = s.get_state()
+        s.set_state(st[0], st[1], st[2], c0 if c0 is not None else None)
+        s.set_time(0.0)
+    reset()
+    return s, reset, np.asarray(b)
+
+
+def cpu_baseline(name, seconds):
+    """The oracle (PyTorch CPU, float64) on a 24x12-cell window of the workload."""
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import build_oracle
+    from workloads import workload
+    wl = workload(name, window=(116, 40, 24, 12)) if name == "beach_dambreak_256" else workload(name)
+    o, _ = build_oracle(wl)
+    from oracle import tableau
+    stages = len(tableau(o.p.rk)[1])
+    nf = 3 + (1 if o.p.tracer else 0)
+    dofs = nf * o.np_ * o.m.K
+    o.step()                      # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step()
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds:
+            break
+    return dict(value=dofs * stages * n / el, unit="DoF-updates/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"oracle on a {o.m.K}-cell window (24x12) of {name}, {n} SSP3 steps after 1 warm-up step, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="beach_dambreak_256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
+              "(the multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from workloads import workload
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (HIP device)", file=sys.stderr)
+        sys.exit(1)
+    dev = "cuda:0"
+    wl = workload(args.workload)
+    s, reset, _ = setup(wl, dev)
+    stages = {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[wl["params"]["rk"]]
+    r = int(wl["params"]["r"])
+    S = int(wl["params"]["S"][0])
+    nf = 3 + (1 if wl["params"]["tracer"] else 0)
+    dofs_stage = nf * (r + 1) ** 2 * s.n_cells
+
+    s.run(args.warmup)
+    s.sync()
+    reset()
+    s.sync()
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        bcopy = torch.empty_like(a)
+        for _ in range(2):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+    s.profile(True)
+    s.kernel_time_reset()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    s.run(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kt = s.kernel_times()
+    s.profile(False)
+    s.sync()
+    diag = s.diagnostics()
+    value = dofs_stage * stages * args.steps / (ms * 1e-3)
+
+    # dominant kernel: the fast element kernel of stages 2..s
+    k_ms, k_n = kt["element_stage"]
+    avg_s = (k_ms / max(k_n, 1)) * 1e-3
+    # stages 2..s combine 1..s-1 stored residuals: average
+    mean_terms = sum(range(1, stages)) / max(stages - 1, 1)
+    bpc, fpc = element_stage_work(S, r, nf, mean_terms)
+    bytes_launch = bpc * s.n_cells
+    flops_launch = fpc * s.n_cells
+    gbs = bytes_launch / avg_s / 1e9
+    tfl = flops_launch / avg_s / 1e12
+    f_hbm, f_fp = gbs / HBM_PEAK_GBS, tfl / FP64_PEAK_TFLOPS
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_sha") == stage_source_sha():
+            traffic = tr.get("bytes_per_launch")
+    if f_hbm >= f_fp:
+        roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(f_hbm, 4))
+    else:
+        roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(f_fp, 4))
+    roof.update(traffic=traffic, kernel=f"k_elem<r={r},P={S},F_STAGE>",
+                launch_ms=round(avg_s * 1e3, 5), algo_bytes_per_launch=bytes_launch,
+                algo_flops_per_launch=flops_launch, hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4),
+                kernel_share={k: round(v[0] / ms, 4) for k, v in kt.items()})
+    line = dict(metric="FP64 DoF-updates/s per RK stage", value=value, unit="DoF-updates/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload=args.workload, cells=s.n_cells, r=r, S=S, rk=wl["params"]["rk"],
+                            stages_per_step=stages, dofs_per_stage=dofs_stage, parallelism="single GPU"),
+                roofline=roof)
+    line["config"]["max_newton_it"] = diag["max_newton_it"]
+    line["config"]["r0_cells"] = diag["n_r0_cells"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,19 @@ sw_status sw_run(sw_ctx *c, int32_t n_steps, double dt);
 
 /* Diagnostics of the last step (host output).  Synchronises. */
 sw_status sw_diagnostics(const sw_ctx *c, sw_diag *out_host);
+/* Kernel timing.  With profiling on, each launch group of a kernel class is
+ * bracketed by HIP events on the context's stream; sw_kernel_time returns the
+ * accumulated milliseconds and kernel launches of one class (synchronises):
+ *   kind 0: fast element kernel at step begin (degree decision, H^n, stage-1 volume terms)
+ *   kind 1: fast element kernel of stages 2..s (solves + volume terms)
+ *   kind 2: fast element kernel of the final combination (+ next step's start)
+ *   kind 3: face kernel
+ *   kind 4: general element kernel (cells the fast kernel leaves, tracer runs).
+ * sw_kernel_time_reset clears the totals. */
+sw_status sw_profile(sw_ctx *c, int32_t on);
+sw_status sw_kernel_time(sw_ctx *c, int32_t kind, double *ms_total, int64_t *launches);
+sw_status sw_kernel_time_reset(sw_ctx *c);
+
 /* Wait for the context's stream; reports SW_EDEVICE if a kernel flagged an error. */
 sw_status sw_sync(sw_ctx *c);
 

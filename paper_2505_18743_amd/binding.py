@@ -21,7 +21,8 @@ RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3}
 EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_counts", "sw_node_coords", "sw_dof_coords",
            "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset", "sw_set_state", "sw_get_state",
            "sw_init_lake_at_rest", "sw_set_time", "sw_apply_operator", "sw_step_begin", "sw_rk_stage",
-           "sw_step_end", "sw_step", "sw_run", "sw_diagnostics", "sw_sync"]
+           "sw_step_end", "sw_step", "sw_run", "sw_diagnostics", "sw_sync", "sw_profile", "sw_kernel_time",
+           "sw_kernel_time_reset"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -84,6 +85,9 @@ def load():
     L.sw_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
     L.sw_diagnostics.argtypes = [vp, ctypes.POINTER(SwDiag)]
     L.sw_sync.argtypes = [vp]
+    L.sw_profile.argtypes = [vp, ctypes.c_int32]
+    L.sw_kernel_time.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.sw_kernel_time_reset.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("sw_destroy", "sw_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -250,6 +254,23 @@ class Solver:
 
     def sync(self):
         _check(load().sw_sync(self.h), "sw_sync")
+
+    def profile(self, on=True):
+        _check(load().sw_profile(self.h, int(bool(on))), "sw_profile")
+
+    KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general")
+
+    def kernel_times(self):
+        """{kernel class: (total ms, launches)} accumulated while profiling."""
+        out = {}
+        for k, name in enumerate(self.KERNELS):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(load().sw_kernel_time(self.h, k, ctypes.byref(ms), ctypes.byref(n)), "sw_kernel_time")
+            out[name] = (ms.value, n.value)
+        return out
+
+    def kernel_time_reset(self):
+        _check(load().sw_kernel_time_reset(self.h), "sw_kernel_time_reset")
 
     def diagnostics(self):
         d = SwDiag()

@@ -35,8 +35,24 @@ __global__ void k_set(double*, int, double);
 __global__ void k_fill(double*, size_t, double);
 __global__ void k_fill8(int8_t*, size_t, int8_t);
 __global__ void k_copy(const double*, double*, size_t);
+__global__ void k_minred(const double*, int, double*);
 __global__ void k_dt(const double*, int, double, double, double*);
+__global__ void k_diag_part(const double*, const int8_t*, int, double*);
 __global__ void k_diag(const double*, int, double*, double*);
+
+hipError_t launch_elem_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+
+hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return launch_elem_r1(P, mode, a, nblk, s);
+    case 2: return launch_elem_r2(P, mode, a, nblk, s);
+    case 3: return launch_elem_r3(P, mode, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
 }  // namespace swk
 
 using namespace swk;
@@ -188,10 +204,12 @@ struct LevelH {
   double dx = 0, w1 = 0;
   int cell0 = 0, ncell = 0;
   size_t off = 0;          // offset of this level's samples in the node arrays
-  int face0 = 0, nface = 0;
-  size_t zfoff = 0;        // offset in the face-sample array
-  int blk0 = 0, nblk = 0;  // element-kernel blocks (diagnostic slots)
-  int fblk0 = 0, fnblk = 0;
+  int face0 = 0, nface = 0;  // all faces whose fine (or equal) side is on this level
+  size_t zfoff = 0;          // offset of this level's faces in the face-sample array
+  // face classes: direction (x: W/E, y: S/N) x (conforming or boundary, sub-face 0,
+  // sub-face 1); the faces of one class touch disjoint (cell, dof) sets
+  int cface0[6]{}, cnface[6]{}, cfblk0[6]{}, cfnblk[6]{};
+  int nblk = 0;              // element-kernel blocks
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
   LevelTabs tabs{};
@@ -210,19 +228,26 @@ struct sw_ctx {
   std::vector<int> lev, ci, cj;
   std::vector<LevelH> lv;
   double A[4][4]{}, b[4]{}, c[4]{};
-  int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_cface = nullptr, *d_err = nullptr;
+  int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr;
   double *d_zb = nullptr, *d_braw = nullptr, *d_db = nullptr, *d_bvec = nullptr, *d_zmax = nullptr;
   double *d_nman = nullptr, *d_cdx = nullptr, *d_cw1 = nullptr, *d_zf = nullptr;
   double *d_sn[4]{}, *d_ss[4]{};
-  double *d_hn = nullptr, *d_cn = nullptr, *d_res = nullptr, *d_fbuf = nullptr;
-  double *d_scal = nullptr, *d_dpart = nullptr, *d_bpart = nullptr, *d_diag = nullptr;
-  int8_t *d_flag = nullptr, *d_allwet = nullptr;
-  int nblk_total = 0, fblk_total = 0;
+  double *d_hn = nullptr, *d_cn = nullptr, *d_res = nullptr;
+  double *d_scal = nullptr, *d_cdiag = nullptr, *d_bpart = nullptr, *d_red = nullptr, *d_diag = nullptr;
+  int8_t *d_flag = nullptr, *d_allwet = nullptr, *d_need = nullptr;
+  int fblk_total = 0;
+  bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
   bool fixed_dt = false;
   bool bathy_set = false;
   int stage_done = 0;      // stages completed in the current step (0: no step open)
   int64_t nstep = 0;
   std::vector<void*> allocs;
+  // kernel timing (sw_profile): events recorded around each launch group
+  bool prof = false;
+  struct Ev { int kind; int nlaunch; hipEvent_t a, b; };
+  std::vector<Ev> ev;
+  double prof_ms[8]{};
+  int64_t prof_n[8]{};
 
   template <class T>
   sw_status alloc(T** p, size_t n) {
@@ -235,8 +260,33 @@ struct sw_ctx {
     return SW_OK;
   }
   ~sw_ctx() {
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
     for (void* q : allocs) (void)hipFree(q);
   }
+  // bracket a group of launches of one kernel class with events when profiling
+  struct Scope {
+    sw_ctx* c;
+    int kind, n;
+    hipEvent_t a{}, b{};
+    bool on = false;
+    Scope(sw_ctx* c_, int k, int n_) : c(c_), kind(k), n(n_) {
+      if (!c->prof) return;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      on = hipEventRecord(a, c->s) == hipSuccess;
+    }
+    ~Scope() {
+      if (!on) return;
+      (void)hipEventRecord(b, c->s);
+      c->ev.push_back({kind, n, a, b});
+    }
+  };
 };
 
 namespace {
@@ -388,17 +438,14 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.hn = c->d_hn;
   a.cn = c->d_cn;
   a.res = c->d_res;
-  a.fbuf = c->d_fbuf;
-  a.cface = c->d_cface;
-  a.nface2 = 2 * c->F;
   a.flag = c->d_flag;
+  a.need = nullptr;
+  a.cdiag = c->d_cdiag;
+  a.diag_init = 0;
   a.allwet = c->d_allwet;
   a.scal = c->d_scal;
-  a.dpart = c->d_dpart;
-  a.dpart0 = L.blk0;
   a.err = c->d_err;
   a.slot = 0;
-  a.fold = -1;
   a.nterm = 0;
   a.g = c->p.g;
   a.eps = c->p.eps;
@@ -411,26 +458,27 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   return a;
 }
 
-FaceArgs face_args(sw_ctx* c, const LevelH& L, const double* const* st, double cstage, double* bpart) {
+FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st, double cstage, int slot) {
   FaceArgs a{};
-  a.face0 = L.face0;
-  a.nface = L.nface;
+  a.face0 = L.cface0[cls];
+  a.nface = L.cnface[cls];
   a.K = c->K;
   a.S = L.S;
   a.fA = c->d_fA;
   a.fB = c->d_fB;
   a.meta = c->d_meta;
-  a.zf = c->d_zf + L.zfoff;
+  a.zf = c->d_zf + L.zfoff + (size_t)(L.cface0[cls] - L.face0) * 2 * L.S;
   for (int f = 0; f < 4; ++f) a.st[f] = st[f];
-  a.fbuf = c->d_fbuf;
+  a.res = c->d_res;
+  a.slot = slot;
   a.cdx = c->d_cdx;
   a.cw1 = c->d_cw1;
   a.fl = L.tabs.fl;
   a.w = L.tabs.w;
   a.scal = c->d_scal;
   a.cstage = cstage;
-  a.bpart = bpart;
-  a.bpart0 = L.fblk0;
+  a.bpart = c->d_bpart;
+  a.bpart0 = L.cfblk0[cls];
   a.err = c->d_err;
   a.g = c->p.g;
   a.eps = c->p.eps;
@@ -442,16 +490,66 @@ FaceArgs face_args(sw_ctx* c, const LevelH& L, const double* const* st, double c
   return a;
 }
 
-sw_status faces(sw_ctx* c, const double* const* st, double cstage) {
+// all face classes of all levels, adding into residual slot `slot`
+sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, const double* scal_override = nullptr) {
+  int n = 0;
+  for (auto& L : c->lv)
+    for (int k = 0; k < 6; ++k) n += L.cnface[k] > 0;
+  sw_ctx::Scope sc(c, 3, n);
+  for (auto& L : c->lv)
+    for (int k = 0; k < 6; ++k) {
+      if (L.cnface[k] == 0) continue;
+      FaceArgs fa = face_args(c, L, k, st, cstage, slot);
+      if (scal_override) fa.scal = scal_override;
+      HIPCHK(launch_face(c->r, L.P, fa, L.cfnblk[k], c->s));
+    }
+  return SW_OK;
+}
+
+// dt = cfl * min of the face kernels' block bounds (two-level reduction)
+sw_status reduce_dt(sw_ctx* c, double cfl, double* dst) {
+  if (c->fblk_total == 0) return SW_OK;
+  const int n1 = (c->fblk_total + 1023) / 1024;
+  hipLaunchKernelGGL(k_minred, dim3(n1), dim3(256), 0, c->s, c->d_bpart, c->fblk_total, c->d_red);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, c->s, c->d_red, n1, cfl, 0.0, dst);
+  HIPCHK(hipGetLastError());
+  return SW_OK;
+}
+
+// element work of one phase on every level: the fast kernel where it applies,
+// then the general kernel on the cells it left (or on all cells)
+sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
+                   int kind) {
+  const bool fast_ok = !c->p.tracer;
   for (auto& L : c->lv) {
-    if (L.nface == 0) continue;
-    FaceArgs fa = face_args(c, L, st, cstage, c->d_bpart);
-    HIPCHK(launch_face(c->r, L.P, fa, L.fnblk, c->s));
+    StageArgs a = stage_args(c, L);
+    a.slot = slot;
+    a.nterm = nterm;
+    for (int m = 0; m < 4; ++m) a.a[m] = coef ? coef[m] : 0.0;
+    a.diag_init = diag_init;
+    if (fast_ok) {
+      sw_ctx::Scope sc(c, kind, 1);
+      a.need = c->d_need;
+      HIPCHK(launch_elem(c->r, L.P, fmode, a, L.nblk, c->s));
+    }
+    StageArgs g = a;
+    g.need = fast_ok ? c->d_need : nullptr;
+    if (gmode >= 0) {
+      sw_ctx::Scope sc(c, 4, 1);
+      HIPCHK(launch_stage(c->r, L.P, gmode, g, L.nblk, c->s));
+    }
+    if (gmode2 >= 0) {
+      sw_ctx::Scope sc(c, 4, 1);
+      g.slot = 0;
+      HIPCHK(launch_stage(c->r, L.P, gmode2, g, L.nblk, c->s));
+    }
   }
   return SW_OK;
 }
 
 sw_status rebake(sw_ctx* c) {
+  c->start_ready = false;
   for (auto& L : c->lv) {
     const size_t n = (size_t)L.ncell * L.S * L.S;
     if (n == 0) continue;
@@ -461,7 +559,7 @@ sw_status rebake(sw_ctx* c) {
   }
   for (auto& L : c->lv) {
     if (L.nface > 0) {
-      const int n = L.nface * L.S;
+      const int n = L.nface * L.S;   // all classes of the level: one contiguous range
       hipLaunchKernelGGL(k_facez, dim3((n + 255) / 256), dim3(256), 0, c->s, c->d_fA, c->d_fB, c->d_meta, L.face0,
                          L.nface, L.S, L.cell0, L.ncell, L.off, c->d_zb, c->d_braw, c->d_db, c->d_zf + L.zfoff,
                          c->d_err, c->K);
@@ -639,48 +737,52 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
       }
     }
   }
-  std::stable_sort(fh.begin(), fh.end(), [](const FaceH& x, const FaceH& y) { return x.lvl < y.lvl; });
+  // class of a face: x or y direction times (conforming/boundary, sub-face 0, sub-face 1)
+  auto cls = [](const FaceH& h) { return (h.sa < 2 ? 0 : 3) + (h.sub + 1); };
+  std::stable_sort(fh.begin(), fh.end(), [&](const FaceH& x, const FaceH& y) {
+    return x.lvl != y.lvl ? x.lvl < y.lvl : cls(x) < cls(y);
+  });
   c->F = (int)fh.size();
-  std::vector<int> fA(c->F), fB(c->F), meta(c->F), cface((size_t)K * 8, -1);
+  std::vector<int> fA(c->F), fB(c->F), meta(c->F), used((size_t)K * 8, 0);
   for (int f = 0; f < c->F; ++f) {
     const FaceH& h = fh[f];
     fA[f] = h.a;
     fB[f] = h.b;
     meta[f] = h.sa | (h.sb << 2) | ((h.sub + 1) << 4) | (h.bnd << 6) | (h.bc << 8);
-    int& ea = cface[(size_t)h.a * 8 + h.sa * 2];
-    if (ea != -1) {
+    // every cell side carries one face, or two sub-faces on a coarse side
+    if (used[(size_t)h.a * 8 + h.sa * 2]++) {
       delete c;
       return fail(SW_EINVAL, "two faces on one cell side");
     }
-    ea = 2 * f;
-    if (!h.bnd) {
-      int& eb = cface[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)];
-      if (eb != -1) {
-        delete c;
-        return fail(SW_EINVAL, "two faces on one cell side");
-      }
-      eb = 2 * f + 1;
+    if (!h.bnd && used[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)]++) {
+      delete c;
+      return fail(SW_EINVAL, "two faces on one cell side");
     }
   }
   {
     int f = 0;
     size_t zo = 0;
-    int blk = 0, fblk = 0;
+    int fblk = 0;
     for (auto& L : c->lv) {
       L.face0 = f;
-      while (f < c->F && fh[f].lvl == L.L) ++f;
+      const int cpb = kWave / L.P;
+      for (int k = 0; k < 6; ++k) {
+        L.cface0[k] = f;
+        while (f < c->F && fh[f].lvl == L.L && cls(fh[f]) == k) ++f;
+        L.cnface[k] = f - L.cface0[k];
+        L.cfnblk[k] = (L.cnface[k] + cpb - 1) / cpb;
+        L.cfblk0[k] = fblk;
+        fblk += L.cfnblk[k];
+      }
       L.nface = f - L.face0;
       L.zfoff = zo;
       zo += (size_t)L.nface * 2 * L.S;
-      const int cpb = kWave / L.P;
       L.nblk = (L.ncell + cpb - 1) / cpb;
-      L.blk0 = blk;
-      blk += L.nblk;
-      L.fnblk = (L.nface + cpb - 1) / cpb;
-      L.fblk0 = fblk;
-      fblk += L.fnblk;
     }
-    c->nblk_total = blk;
+    if (f != c->F) {
+      delete c;
+      return fail(SW_EINVAL, "internal: face classes do not cover the face list");
+    }
     c->fblk_total = fblk;
     sw_status st = SW_OK;
     const size_t KN = (size_t)K * c->NP;
@@ -692,7 +794,6 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
     ALLOC(c->d_fA, c->F);
     ALLOC(c->d_fB, c->F);
     ALLOC(c->d_meta, c->F);
-    ALLOC(c->d_cface, (size_t)K * 8);
     ALLOC(c->d_err, 1);
     ALLOC(c->d_zb, (size_t)c->nvol);
     ALLOC(c->d_braw, (size_t)c->nvol);
@@ -710,10 +811,11 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
     ALLOC(c->d_hn, KN);
     ALLOC(c->d_cn, KN);
     ALLOC(c->d_res, (size_t)kNSlot * 4 * KN);
-    ALLOC(c->d_fbuf, (size_t)c->F * 8 * c->N1);
     ALLOC(c->d_scal, 8);
-    ALLOC(c->d_dpart, (size_t)c->nblk_total * D_NSLOT);
+    ALLOC(c->d_cdiag, (size_t)K * D_NSLOT);
     ALLOC(c->d_bpart, (size_t)std::max(c->fblk_total, 1));
+    ALLOC(c->d_red, (size_t)std::max((c->fblk_total + 1023) / 1024, (K + 255) / 256) * D_NSLOT);
+    ALLOC(c->d_need, K);
     ALLOC(c->d_diag, 16);
     ALLOC(c->d_flag, K);
     ALLOC(c->d_allwet, K);
@@ -735,7 +837,6 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
   HIPCHK(hipMemcpy(c->d_fA, fA.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_fB, fB.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_meta, meta.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_cface, cface.data(), sizeof(int) * cface.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_cdx, cdx.data(), sizeof(double) * K, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_cw1, cw1.data(), sizeof(double) * K, hipMemcpyHostToDevice));
   HIPCHK(hipMemset(c->d_err, 0, sizeof(int)));
@@ -743,8 +844,8 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
   HIPCHK(hipMemset(c->d_nman, 0, sizeof(double) * K));
   HIPCHK(hipMemset(c->d_scal, 0, sizeof(double) * 8));
   HIPCHK(hipMemset(c->d_diag, 0, sizeof(double) * 16));
-  HIPCHK(hipMemset(c->d_dpart, 0, sizeof(double) * (size_t)c->nblk_total * D_NSLOT));
-  HIPCHK(hipMemset(c->d_fbuf, 0, sizeof(double) * (size_t)c->F * 8 * c->N1));
+  HIPCHK(hipMemset(c->d_cdiag, 0, sizeof(double) * (size_t)K * D_NSLOT));
+  HIPCHK(hipMemset(c->d_need, 0, K));
   HIPCHK(hipMemset(c->d_res, 0, sizeof(double) * (size_t)kNSlot * 4 * K * c->NP));
   HIPCHK(hipMemset(c->d_flag, c->r, K));
   HIPCHK(hipMemset(c->d_allwet, 0, K));
@@ -832,6 +933,7 @@ sw_status sw_set_manning(sw_ctx* c, const double* n) {
   if (st != SW_OK) return st;
   hipLaunchKernelGGL(k_copy, dim3((c->K + 255) / 256), dim3(256), 0, c->s, n, c->d_nman, (size_t)c->K);
   HIPCHK(hipGetLastError());
+  c->start_ready = false;
   return SW_OK;
 }
 
@@ -850,6 +952,7 @@ sw_status sw_set_state(sw_ctx* c, const double* eta, const double* qx, const dou
                      (int8_t)c->r);
   HIPCHK(hipGetLastError());
   c->stage_done = 0;
+  c->start_ready = false;
   return SW_OK;
 }
 
@@ -881,6 +984,7 @@ sw_status sw_init_lake_at_rest(sw_ctx* c, const double* eta) {
                      (int8_t)c->r);
   HIPCHK(hipGetLastError());
   c->stage_done = 0;
+  c->start_ready = false;
   return SW_OK;
 }
 
@@ -898,6 +1002,7 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
   if (c->p.tracer && (!tr || !R)) return fail(SW_EINVAL, "tracer and R are required with a tracer");
   sw_status st = need_bathy(c);
   if (st != SW_OK) return st;
+  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_apply_operator cannot run inside an open step");
   // the elevation boundary reads the time from scal[1]: evaluate at t with dt = 0
   hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, c->d_scal, 3, t);
   for (auto& L : c->lv) {
@@ -910,25 +1015,25 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
     HIPCHK(launch_stage(c->r, L.P, M_APPLY, a, L.nblk, c->s));
   }
   const double* st4[4] = {eta, qx, qy, c->p.tracer ? tr : eta};
-  for (auto& L : c->lv) {
-    if (L.nface == 0) continue;
-    FaceArgs fa = face_args(c, L, st4, 0.0, c->d_bpart);
-    fa.scal = c->d_scal + 2;   // the face kernel reads t from scal[1] = d_scal[3] (cstage = 0)
-    HIPCHK(launch_face(c->r, L.P, fa, L.fnblk, c->s));
-  }
+  // the face kernel reads t from scal[1] = d_scal[3] (cstage = 0)
+  if ((st = faces(c, st4, 0.0, kApplySlot, c->d_scal + 2)) != SW_OK) return st;
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
-    a.fold = kApplySlot;
+    a.slot = kApplySlot;
     a.out[0] = F;
     a.out[1] = Gx;
     a.out[2] = Gy;
     a.out[3] = c->p.tracer ? R : nullptr;
     HIPCHK(launch_stage(c->r, L.P, M_FOLD, a, L.nblk, c->s));
   }
-  if (dtb && c->fblk_total > 0) {
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, c->s, c->d_bpart, c->fblk_total, 1.0, 0.0, dtb);
-    HIPCHK(hipGetLastError());
+  if (dtb) {
+    if (c->fblk_total > 0) {
+      if ((st = reduce_dt(c, 1.0, dtb)) != SW_OK) return st;
+    } else {
+      hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, dtb, 0, 1e300);
+    }
   }
+  c->start_ready = false;   // the apply slot does not disturb the step's data, but stay safe
   return SW_OK;
 }
 
@@ -939,17 +1044,15 @@ sw_status sw_step_begin(sw_ctx* c, double dt) {
   if (c->stage_done != 0) return fail(SW_EINVAL, "a step is already open (call sw_rk_stage / sw_step_end)");
   c->fixed_dt = dt > 0.0;
   if (c->fixed_dt) hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, c->d_scal, 0, dt);
-  for (auto& L : c->lv) {
-    StageArgs a = stage_args(c, L);
-    a.slot = 0;
-    HIPCHK(launch_stage(c->r, L.P, M_START, a, L.nblk, c->s));
-  }
+  // degree adaptation, H(zeta^n) and stage-1 volume terms (already in place after
+  // a previous step's final kernel)
+  if (!c->start_ready)
+    if ((st = elements(c, F_START, M_START, -1, 0, 0, nullptr, 0, 0)) != SW_OK) return st;
   const double* stn[4] = {c->d_sn[0], c->d_sn[1], c->d_sn[2], c->d_sn[3]};
-  if ((st = faces(c, stn, c->c[0])) != SW_OK) return st;
-  if (!c->fixed_dt && c->fblk_total > 0) {
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, c->s, c->d_bpart, c->fblk_total, c->p.cfl, 0.0, c->d_scal);
-    HIPCHK(hipGetLastError());
-  }
+  if ((st = faces(c, stn, c->c[0], 0)) != SW_OK) return st;
+  if (!c->fixed_dt)
+    if ((st = reduce_dt(c, c->p.cfl, c->d_scal)) != SW_OK) return st;
+  c->start_ready = false;
   c->stage_done = 1;
   return SW_OK;
 }
@@ -958,17 +1061,12 @@ sw_status sw_rk_stage(sw_ctx* c, int32_t l) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (l < 2 || l > c->ns) return fail(SW_EINVAL, "stage index out of range");
   if (c->stage_done != l - 1) return fail(SW_EINVAL, "stages must be taken in order after sw_step_begin");
-  for (auto& L : c->lv) {
-    StageArgs a = stage_args(c, L);
-    a.slot = l - 1;
-    a.fold = l - 2;
-    a.nterm = l - 1;
-    for (int m = 0; m < 4; ++m) a.a[m] = m < l - 1 ? c->A[l - 1][m] : 0.0;
-    HIPCHK(launch_stage(c->r, L.P, M_STAGE, a, L.nblk, c->s));
-  }
-  const double* sts[4] = {c->d_ss[0], c->d_ss[1], c->d_ss[2], c->d_ss[3]};
-  sw_status st = faces(c, sts, c->c[l - 1]);
+  double coef[4];
+  for (int m = 0; m < 4; ++m) coef[m] = m < l - 1 ? c->A[l - 1][m] : 0.0;
+  sw_status st = elements(c, F_STAGE, M_STAGE, -1, l - 1, l - 1, coef, l == 2 ? 1 : 0, 1);
   if (st != SW_OK) return st;
+  const double* sts[4] = {c->d_ss[0], c->d_ss[1], c->d_ss[2], c->d_ss[3]};
+  if ((st = faces(c, sts, c->c[l - 1], l - 1)) != SW_OK) return st;
   c->stage_done = l;
   return SW_OK;
 }
@@ -976,16 +1074,16 @@ sw_status sw_rk_stage(sw_ctx* c, int32_t l) {
 sw_status sw_step_end(sw_ctx* c) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (c->stage_done != c->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
-  for (auto& L : c->lv) {
-    StageArgs a = stage_args(c, L);
-    a.fold = c->ns - 1;
-    a.nterm = c->ns;
-    for (int m = 0; m < 4; ++m) a.a[m] = c->b[m];
-    HIPCHK(launch_stage(c->r, L.P, M_FINAL, a, L.nblk, c->s));
-  }
-  hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, c->s, c->d_dpart, c->nblk_total, c->d_diag, c->d_scal);
+  // final combination; the same pass prepares the next step's start (slot 0)
+  sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2);
+  if (st != SW_OK) return st;
+  const int nb = (c->K + 255) / 256;
+  hipLaunchKernelGGL(k_diag_part, dim3(nb), dim3(256), 0, c->s, c->d_cdiag, c->d_flag, c->K, c->d_red);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, c->s, c->d_red, nb, c->d_diag, c->d_scal);
   HIPCHK(hipGetLastError());
   c->stage_done = 0;
+  c->start_ready = true;
   ++c->nstep;
   return SW_OK;
 }
@@ -1012,6 +1110,43 @@ sw_status sw_sync(sw_ctx* c) {
   int err = 0;
   HIPCHK(hipMemcpy(&err, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (err) return fail(SW_EDEVICE, "a kernel reported an invalid index (code " + std::to_string(err) + ")");
+  return SW_OK;
+}
+
+sw_status sw_profile(sw_ctx* c, int32_t on) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  c->prof = on != 0;
+  return SW_OK;
+}
+
+sw_status sw_kernel_time(sw_ctx* c, int32_t kind, double* ms_total, int64_t* launches) {
+  if (!c || !ms_total || !launches) return fail(SW_EINVAL, "NULL argument");
+  if (kind < 0 || kind > 4) return fail(SW_EINVAL, "kind must be 0..4");
+  for (auto& e : c->ev) {
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    c->prof_ms[e.kind] += ms;
+    c->prof_n[e.kind] += e.nlaunch;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->ev.clear();
+  *ms_total = c->prof_ms[kind];
+  *launches = c->prof_n[kind];
+  return SW_OK;
+}
+
+sw_status sw_kernel_time_reset(sw_ctx* c) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  double ms;
+  int64_t n;
+  sw_status st = sw_kernel_time(c, 0, &ms, &n);
+  if (st != SW_OK) return st;
+  for (int k = 0; k < 8; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
   return SW_OK;
 }
 

@@ -110,16 +110,22 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
   const double wl = act ? A.w[al] * dxA : 0.0;
   const double cAv[4] = {-mass, -momx + pres * nx, -momy + pres * ny, -trac};
   const double cBv[4] = {mass, momx + pres * nx, momy + pres * ny, trac};
-  double* out = A.fbuf + (size_t)f * 8 * N1;
+  // add the projections onto the face test functions of both sides into the
+  // residual slot; faces of one launch touch disjoint (cell, dof) sets
+  const size_t KN = (size_t)A.K * NP;
+  double* rA = A.res + (size_t)A.slot * 4 * KN + (size_t)cA * NP;
+  double* rB = A.res + (size_t)A.slot * 4 * KN + (size_t)cB * NP;
+  const int nq = A.tracer ? 4 : 3;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
+    if (q >= nq) break;
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const double va = gsum<P>(wl * cAv[q] * la[k]);
-      const double vb = gsum<P>(bnd ? 0.0 : wl * cBv[q] * lb[k]);
-      const int ia = q * N1 + k, ib = 4 * N1 + q * N1 + k;
-      if (fv && ok && (ia % P) == lane) out[ia] = va;
-      if (fv && ok && (ib % P) == lane) out[ib] = vb;
+      const double vb = gsum<P>(wl * cBv[q] * lb[k]);
+      const int ia = q * N1 + k;
+      if (fv && ok && (ia % P) == lane) rA[(size_t)q * KN + row_dof<R>(sA, k)] += va;
+      if (fv && ok && !bnd && ((ia + 2 * N1) % P) == lane) rB[(size_t)q * KN + row_dof<R>(sB, k)] += vb;
     }
   }
   // positivity time-step bound (Prop. 3.2): w J_K / (lambda l_Gamma) on both sides

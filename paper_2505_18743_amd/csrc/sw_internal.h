@@ -15,8 +15,9 @@ enum Mode : int {
   M_START = 2,  // degree adaptation, remap, H^n, C~^n, stage-1 volume residual
   M_STAGE = 3,  // stage-l solves from stored residuals + volume residual
   M_FINAL = 4,  // final combination + solves + mass diagnostics
-  M_TRACER = 5  // tracer-only replay of a stored stage
 };
+// fast element kernel modes (see k_elem)
+enum FastMode : int { F_START = 0, F_STAGE = 1, F_FINAL = 2 };
 
 // per-level reference tables on the device
 struct LevelTabs {
@@ -47,18 +48,16 @@ struct StageArgs {
   double* out[4];        // M_FOLD outputs
   double* hn;            // [K][NP] H(zeta^n)
   double* cn;            // [K][NP] C~^n
-  double* res;           // [NS][4][K][NP]
-  const double* fbuf;    // [F][2][4][N1]
-  const int* cface;      // [K][8]
-  int nface2;            // 2 * number of faces (bound of cface entries)
+  double* res;           // [NS][4][K][NP] residual slots (volume + face terms)
   int8_t* flag;          // [K] current degree (r or 0)
+  int8_t* need;          // [K] cells left to the general kernel (fast kernel writes,
+                         //     general kernel reads: only flagged cells are processed)
+  double* cdiag;         // [K][D_NSLOT] per-cell diagnostics of the current step
+  int diag_init;         // 1: first solve of the step initialises cdiag
   int8_t* allwet;        // [K] zeta^n wet at every sample node
   const double* scal;    // device scalars: [0] dt, [1] t
-  double* dpart;         // [nblk_total][D_NSLOT]
-  int dpart0;            // first block slot of this launch
   int* err;
-  int slot;              // residual slot written (M_APPLY/M_START/M_STAGE) or folded
-  int fold;              // residual slot to fold (M_STAGE/M_FINAL), -1 none
+  int slot;              // residual slot written (volume terms) or copied (M_FOLD)
   int nterm;             // number of stored residuals combined
   double a[4];           // combination weights a_{l,m} or b_m
   double g, eps, hlim, eps0;
@@ -72,7 +71,8 @@ struct FaceArgs {
   const int* meta;       // sideA | sideB<<2 | (sub+1)<<4 | boundary<<6 | bc<<8
   const double* zf;      // group block [nface][2][S]
   const double* st[4];
-  double* fbuf;          // [F][2][4][N1]
+  double* res;           // [NS][4][K][NP] residual slots
+  int slot;              // slot receiving the face terms
   const double* cdx;     // [K]
   const double* cw1;     // [K]
   const double* fl;      // [3][S][N1]
@@ -89,6 +89,7 @@ struct FaceArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s);
 
 inline int lanes_for(int S) {

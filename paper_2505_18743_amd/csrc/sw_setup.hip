@@ -131,52 +131,104 @@ __global__ void k_copy(const double* a, double* b, size_t n) {
   if (t < n) b[t] = a[t];
 }
 
-// dt = cfl * min(block bounds) (or the fixed dt when fixed > 0); single block.
-__global__ void k_dt(const double* bpart, int n, double cfl, double fixed, double* dst) {
+// Block-wise minimum: out[b] = min(in[b*1024 .. b*1024+1023]).
+__global__ void k_minred(const double* in, int n, double* out) {
   __shared__ double sm[256];
+  const int base = blockIdx.x * 1024 + threadIdx.x;
   double m = 1e300;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmin(m, bpart[i]);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u * 256;
+    if (i < n) m = fmin(m, in[i]);
+  }
   sm[threadIdx.x] = m;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+// dt = cfl * min(in[0..n)) (or the fixed dt when fixed > 0); one block of 256.
+__global__ void k_dt(const double* in, int n, double cfl, double fixed, double* dst) {
+  __shared__ double sm[256];
+  double m = 1e300;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, in[i]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) *dst = fixed > 0.0 ? fixed : cfl * sm[0];
 }
 
-// End of step: reduce block partials (fixed order) and advance t.
-__global__ void k_diag(const double* dpart, int n, double* diag, double* scal) {
-  __shared__ double s0[256], s1[256], s2[256], s3[256], s4[256], s5[256], s6[256];
-  double mt = 1e300, vi = 0, nw = 0, fb = 0, ms = 0, nr = 0, nf = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double* d = dpart + (size_t)i * D_NSLOT;
-    mt = fmin(mt, d[D_MINT]);
-    vi += d[D_VIOL];
-    nw = fmax(nw, d[D_NEWT]);
-    fb += d[D_FALLB];
-    ms += d[D_MASS];
-    nr += d[D_NR0];
-    nf = fmax(nf, d[D_NONF]);
-  }
+// Per-cell diagnostics -> per-block partials (256 cells per block).
+__global__ void k_diag_part(const double* cdiag, const int8_t* flag, int K, double* part) {
+  __shared__ double s[D_NSLOT][256];
   const int t = threadIdx.x;
-  s0[t] = mt; s1[t] = vi; s2[t] = nw; s3[t] = fb; s4[t] = ms; s5[t] = nr; s6[t] = nf;
+  const int c = blockIdx.x * 256 + t;
+  double v[D_NSLOT] = {1e300, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c < K) {
+    const double* d = cdiag + (size_t)c * D_NSLOT;
+    v[D_MINT] = d[D_MINT];
+    v[D_VIOL] = d[D_VIOL];
+    v[D_NEWT] = d[D_NEWT];
+    v[D_FALLB] = d[D_FALLB];
+    v[D_MASS] = d[D_MASS];
+    v[D_NR0] = flag[c] == 0 ? 1.0 : 0.0;
+    v[D_NONF] = d[D_NONF];
+  }
+  for (int q = 0; q < D_NSLOT; ++q) s[q][t] = v[q];
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      s0[t] = fmin(s0[t], s0[t + s]);
-      s1[t] += s1[t + s];
-      s2[t] = fmax(s2[t], s2[t + s]);
-      s3[t] += s3[t + s];
-      s4[t] += s4[t + s];
-      s5[t] += s5[t + s];
-      s6[t] = fmax(s6[t], s6[t + s]);
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st) {
+      s[D_MINT][t] = fmin(s[D_MINT][t], s[D_MINT][t + st]);
+      s[D_VIOL][t] += s[D_VIOL][t + st];
+      s[D_NEWT][t] = fmax(s[D_NEWT][t], s[D_NEWT][t + st]);
+      s[D_FALLB][t] += s[D_FALLB][t + st];
+      s[D_MASS][t] += s[D_MASS][t + st];
+      s[D_NR0][t] += s[D_NR0][t + st];
+      s[D_NONF][t] = fmax(s[D_NONF][t], s[D_NONF][t + st]);
+    }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int q = 0; q < D_NSLOT; ++q) part[(size_t)blockIdx.x * D_NSLOT + q] = s[q][0];
+}
+
+// End of step: reduce the block partials in a fixed order and advance t.
+__global__ void k_diag(const double* part, int n, double* diag, double* scal) {
+  __shared__ double s[D_NSLOT][256];
+  const int t = threadIdx.x;
+  double v[D_NSLOT] = {1e300, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = t; i < n; i += 256) {
+    const double* d = part + (size_t)i * D_NSLOT;
+    v[D_MINT] = fmin(v[D_MINT], d[D_MINT]);
+    v[D_VIOL] += d[D_VIOL];
+    v[D_NEWT] = fmax(v[D_NEWT], d[D_NEWT]);
+    v[D_FALLB] += d[D_FALLB];
+    v[D_MASS] += d[D_MASS];
+    v[D_NR0] += d[D_NR0];
+    v[D_NONF] = fmax(v[D_NONF], d[D_NONF]);
+  }
+  for (int q = 0; q < D_NSLOT; ++q) s[q][t] = v[q];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st) {
+      s[D_MINT][t] = fmin(s[D_MINT][t], s[D_MINT][t + st]);
+      s[D_VIOL][t] += s[D_VIOL][t + st];
+      s[D_NEWT][t] = fmax(s[D_NEWT][t], s[D_NEWT][t + st]);
+      s[D_FALLB][t] += s[D_FALLB][t + st];
+      s[D_MASS][t] += s[D_MASS][t + st];
+      s[D_NR0][t] += s[D_NR0][t + st];
+      s[D_NONF][t] = fmax(s[D_NONF][t], s[D_NONF][t + st]);
     }
     __syncthreads();
   }
   if (t == 0) {
-    diag[0] = s0[0]; diag[1] = s1[0]; diag[2] = s2[0]; diag[3] = s3[0];
-    diag[4] = s4[0]; diag[5] = s5[0]; diag[6] = s6[0];
+    for (int q = 0; q < D_NSLOT; ++q) diag[q] = s[q][0];
     diag[7] = scal[0];
     scal[1] += scal[0];
     diag[8] = scal[1];

@@ -16,12 +16,33 @@ static hipError_t stage_p(int mode, const StageArgs& a, int nblk, hipStream_t s)
   return hipGetLastError();
 }
 
+template <int P>
+static hipError_t elem_p(int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (mode) {
+    case F_START: hipLaunchKernelGGL((k_elem<3, P, F_START>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case F_STAGE: hipLaunchKernelGGL((k_elem<3, P, F_STAGE>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case F_FINAL: hipLaunchKernelGGL((k_elem<3, P, F_FINAL>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_stage_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
   switch (P) {
     case 4: return stage_p<4>(mode, a, nblk, s);
     case 8: return stage_p<8>(mode, a, nblk, s);
     case 16: return stage_p<16>(mode, a, nblk, s);
     case 32: return stage_p<32>(mode, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_elem_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (P) {
+    case 4: return elem_p<4>(mode, a, nblk, s);
+    case 8: return elem_p<8>(mode, a, nblk, s);
+    case 16: return elem_p<16>(mode, a, nblk, s);
+    case 32: return elem_p<32>(mode, a, nblk, s);
   }
   return hipErrorInvalidValue;
 }
