@@ -350,7 +350,8 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   std::vector<double> tab;
   const size_t o_w = 0, o_l = o_w + S, o_d = o_l + (size_t)S * N1, o_m0 = o_d + (size_t)S * N1,
                o_mq = o_m0 + (size_t)NP * NP, o_mean = o_mq + (size_t)NP * NP, o_fl = o_mean + NP,
-               total = o_fl + (size_t)3 * S * N1;
+               o_dp = o_fl + (size_t)3 * S * N1, o_wl = o_dp + (size_t)S * N1, o_wdp = o_wl + (size_t)S * N1,
+               total = o_wdp + (size_t)S * N1;
   tab.assign(total, 0.0);
   for (int a = 0; a < S; ++a) {
     tab[o_w + a] = L.wh[a];
@@ -360,6 +361,9 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
       tab[o_fl + (0 * S + a) * N1 + k] = lag(xi, k, L.xh[a]);
       tab[o_fl + (1 * S + a) * N1 + k] = lag(xi, k, 0.5 * L.xh[a]);
       tab[o_fl + (2 * S + a) * N1 + k] = lag(xi, k, 0.5 * (1.0 + L.xh[a]));
+      tab[o_dp + a * N1 + k] = dlag(xi, k, L.xh[a]) / L.dx;
+      tab[o_wl + a * N1 + k] = L.wh[a] * lag(xi, k, L.xh[a]);
+      tab[o_wdp + a * N1 + k] = L.wh[a] * dlag(xi, k, L.xh[a]) / L.dx;
     }
   }
   // all-wet mass matrix of the sample rule on the unit square, and its inverse
@@ -408,6 +412,9 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.mqinv = L.d_tab + o_mq;
   L.tabs.meanw = L.d_tab + o_mean;
   L.tabs.fl = L.d_tab + o_fl;
+  L.tabs.dp = L.d_tab + o_dp;
+  L.tabs.wl = L.d_tab + o_wl;
+  L.tabs.wdp = L.d_tab + o_wdp;
   L.tabs.S = S;
   L.tabs.dx = L.dx;
   L.w1 = L.wh[0];
@@ -770,7 +777,7 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
         L.cface0[k] = f;
         while (f < c->F && fh[f].lvl == L.L && cls(fh[f]) == k) ++f;
         L.cnface[k] = f - L.cface0[k];
-        L.cfnblk[k] = (L.cnface[k] + cpb - 1) / cpb;
+        L.cfnblk[k] = (L.cnface[k] + kWave / kFaceLanes - 1) / (kWave / kFaceLanes);
         L.cfblk0[k] = fblk;
         fblk += L.cfnblk[k];
       }

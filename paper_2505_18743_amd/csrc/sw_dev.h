@@ -4,30 +4,76 @@
 
 namespace swk {
 
-// Butterfly reductions over groups of P consecutive lanes (P a power of two);
-// every lane of the group receives the result.
+// Cross-lane moves within groups of P consecutive lanes (P a power of two):
+// DPP quad permutations and row mirrors (within 16 lanes), a ds_bpermute for
+// the larger strides.  Every lane of a group takes part in the same call.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+// partner value for butterfly step m (m = 1, 2, 4, 8, 16, 32)
+template <int M>
+__device__ __forceinline__ double partner(double v) {
+  if constexpr (M == 1) return dpp_d<0xB1>(v);        // quad_perm(1,0,3,2)
+  else if constexpr (M == 2) return dpp_d<0x4E>(v);   // quad_perm(2,3,0,1)
+  else if constexpr (M == 4) return dpp_d<0x141>(v);  // row_half_mirror
+  else if constexpr (M == 8) return dpp_d<0x140>(v);  // row_mirror
+  else return __shfl_xor(v, M);
+}
+template <int M>
+__device__ __forceinline__ int partner_i(int v) {
+  if constexpr (M == 1) return dpp_i<0xB1>(v);
+  else if constexpr (M == 2) return dpp_i<0x4E>(v);
+  else if constexpr (M == 4) return dpp_i<0x141>(v);
+  else if constexpr (M == 8) return dpp_i<0x140>(v);
+  else return __shfl_xor(v, M);
+}
+// After the quad steps every lane of a quad holds the quad result, so the
+// mirrors combine whole quads (half rows) exactly like an xor butterfly.
 template <int P>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int m = P / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  if constexpr (P >= 2) v += partner<1>(v);
+  if constexpr (P >= 4) v += partner<2>(v);
+  if constexpr (P >= 8) v += partner<4>(v);
+  if constexpr (P >= 16) v += partner<8>(v);
+  if constexpr (P >= 32) v += partner<16>(v);
+  if constexpr (P >= 64) v += partner<32>(v);
   return v;
 }
 template <int P>
 __device__ __forceinline__ double gmin(double v) {
-#pragma unroll
-  for (int m = P / 2; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
+  if constexpr (P >= 2) v = fmin(v, partner<1>(v));
+  if constexpr (P >= 4) v = fmin(v, partner<2>(v));
+  if constexpr (P >= 8) v = fmin(v, partner<4>(v));
+  if constexpr (P >= 16) v = fmin(v, partner<8>(v));
+  if constexpr (P >= 32) v = fmin(v, partner<16>(v));
+  if constexpr (P >= 64) v = fmin(v, partner<32>(v));
   return v;
 }
 template <int P>
 __device__ __forceinline__ int gand(int v) {
-#pragma unroll
-  for (int m = P / 2; m >= 1; m >>= 1) v &= __shfl_xor(v, m);
+  if constexpr (P >= 2) v &= partner_i<1>(v);
+  if constexpr (P >= 4) v &= partner_i<2>(v);
+  if constexpr (P >= 8) v &= partner_i<4>(v);
+  if constexpr (P >= 16) v &= partner_i<8>(v);
+  if constexpr (P >= 32) v &= partner_i<16>(v);
+  if constexpr (P >= 64) v &= partner_i<32>(v);
   return v;
 }
 template <int P>
 __device__ __forceinline__ int gor(int v) {
-#pragma unroll
-  for (int m = P / 2; m >= 1; m >>= 1) v |= __shfl_xor(v, m);
+  if constexpr (P >= 2) v |= partner_i<1>(v);
+  if constexpr (P >= 4) v |= partner_i<2>(v);
+  if constexpr (P >= 8) v |= partner_i<4>(v);
+  if constexpr (P >= 16) v |= partner_i<8>(v);
+  if constexpr (P >= 32) v |= partner_i<16>(v);
+  if constexpr (P >= 64) v |= partner_i<32>(v);
   return v;
 }
 
@@ -36,6 +82,67 @@ __device__ __forceinline__ double inv_des(double h, double eps) {
   const double h4 = (h * h) * (h * h);
   const double e4 = (eps * eps) * (eps * eps);
   return 1.4142135623730951 * h / sqrt(fmax(h4, e4) + h4);
+}
+
+// 1/x for finite x > 0: hardware reciprocal estimate refined by two Newton
+// steps y <- y + y (1 - x y) (each step squares the relative error).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// x^{-1/2} for finite x > 0: hardware estimate and two Newton steps
+// y <- y (3 - x y^2) / 2.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// x^{-1/3} for finite x > 0: single-precision 2^{-log2(x)/3} as the start, then
+// two Newton steps on z^{-3} = x, z <- z + z (1 - x z^3) / 3.
+__device__ __forceinline__ double rcbrt_nr(double x) {
+  const float xf = (float)x;
+  double z = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * 0.333333343f);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-x, z * z * z, 1.0);
+    z = fma(z * e, 0.3333333333333333, z);
+  }
+  return z;
+}
+
+// Pointwise factors of the volume terms at one node: ih = 1/h_des (eq:velocity)
+// and gam = g n^2 |q| h_des^{-7/3} (eq:manning with the desingularised depth).
+// For h >= eps the definition gives h_des = h exactly, evaluated through the
+// reciprocal and inverse-cube-root iterations; below eps (thin layers, dry
+// nodes) the definition is evaluated as written.
+__device__ __forceinline__ void pointwise(double h, double qx, double qy, double eps, double gn2, bool fric,
+                                          double& ih, double& gam) {
+  gam = 0.0;
+  double hd;                     // h_des = 1/ih, the depth the friction law sees
+  if (h >= eps) {
+    ih = rcp_nr(h);
+    hd = h;
+  } else if (h > 0.0) {
+    // below eps: ih = sqrt(2) h / sqrt(eps^4 + h^4) (the max picks eps^4)
+    const double h2 = h * h, e2 = eps * eps;
+    ih = 1.4142135623730951 * h * rsq_nr(fma(e2, e2, h2 * h2));
+    hd = rcp_nr(ih);
+  } else {
+    ih = 0.0;                    // dry node: no velocity, no friction
+    return;
+  }
+  if (fric) {
+    const double q2 = qx * qx + qy * qy;
+    const double qn = q2 > 0.0 ? q2 * rsq_nr(q2) : 0.0;
+    gam = gn2 * qn * (ih * ih) * rcbrt_nr(hd);
+  }
 }
 
 }  // namespace swk

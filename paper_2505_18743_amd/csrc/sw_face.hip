@@ -1,15 +1,16 @@
 // Face kernel of the sub-grid DG shallow-water operator (gfx950, FP64).
 //
-// One face per group of P = pow2 >= S lanes, lane alpha owning face node
-// alpha of the fine (or equal) side's closed S-point rule, whose nodes are the
-// boundary row of that side's sample grid.  Each lane reconstructs both traces
-// from the (r+1) nodal coefficients of the face row (GLL support points include
-// the element end points, so the trace depends on that row only), applies
-// hydrostatic reconstruction (eq:hydro_rec, eq:hydro_rec_vars) and the Rusanov
-// flux (eq:lxf_parameter), and the projections onto the (r+1) face test
-// functions of each side are finished by a butterfly over the face's lanes.
-// The result goes to a per-face buffer that the element kernel of the next
-// stage gathers in a fixed order (no floating-point atomics).
+// One face per group of kFaceLanes lanes; the lanes split the face nodes (the
+// fine or equal side's closed S-point rule, whose nodes are the boundary row of
+// that side's sample grid).  At each node both traces come from the (r+1)
+// nodal coefficients of the face row (GLL support points include the element
+// end points, so the trace depends on that row only); hydrostatic
+// reconstruction (eq:hydro_rec, eq:hydro_rec_vars) and the Rusanov flux
+// (eq:lxf_parameter) give the flux, and the projections onto the (r+1) face
+// test functions of each side are summed in registers, finished over the
+// face's lanes with DPP moves and added into the stage's residual slot.  The
+// faces of one launch touch disjoint (cell, dof) sets (one face class per
+// launch), so no floating-point atomics are needed.
 #include "sw_dev.h"
 
 namespace swk {
@@ -20,119 +21,147 @@ __device__ __forceinline__ int row_dof(int side, int k) {
   return side == 0 ? k * N1 : side == 1 ? k * N1 + R : side == 2 ? k : R * N1 + k;
 }
 
-template <int R, int P>
+template <int R, int Q, int NQ>
 __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
-  constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / P;
+  constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
   const int S = A.S;
-  const int tid = threadIdx.x, lane = tid % P, lf = tid / P;
+  const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
   const int fl = blockIdx.x * FPB + lf;
   const bool fv = fl < A.nface;
   const int flc = fv ? fl : 0;
   const int f = A.face0 + flc;
-  const bool node = fv && lane < S;
-  const int al = node ? lane : 0;
   int cA = A.fA[f], cB = A.fB[f];
   const int meta = A.meta[f];
   const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
   const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 3;
   const bool ok = (cA >= 0 && cA < A.K) && (bnd || (cB >= 0 && cB < A.K));
-  if (!ok && node) atomicOr(A.err, 2);
-  const bool act = node && ok;
+  if (!ok && fv && lane == 0) atomicOr(A.err, 2);
+  const bool act = fv && ok;
   if (!ok) cA = cB = 0;
   if (bnd) cB = cA;
+  constexpr int nq = NQ;   // fields: zeta, qx, qy (+ tracer)
 
-  double la[N1], lb[N1];
-  const double* tA = A.fl + (size_t)al * N1;
-  const double* tB = A.fl + ((size_t)(sub < 0 ? 0 : 1 + sub) * S + al) * N1;
+  // face-row coefficients of both sides (GLL support points include the end
+  // points, so each trace is the 1-D interpolant of that row)
+  double cfA[NQ][N1], cfB[NQ][N1];
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    la[k] = tA[k];
-    lb[k] = tB[k];
-  }
-  double vA[4], vB[4];
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double sa = 0.0, sb = 0.0;
-    if (q < 3 || A.tracer) {
-      const double* sp = A.st[q];
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        sa += la[k] * sp[(size_t)cA * NP + row_dof<R>(sA, k)];
-        sb += lb[k] * sp[(size_t)cB * NP + row_dof<R>(sB, k)];
-      }
+    for (int k = 0; k < N1; ++k) {
+      const bool use = q < nq;
+      cfA[q][k] = use ? A.st[q][(size_t)cA * NP + row_dof<R>(sA, k)] : 0.0;
+      cfB[q][k] = use ? A.st[q][(size_t)cB * NP + row_dof<R>(sB, k)] : 0.0;
     }
-    vA[q] = sa;
-    vB[q] = sb;
-  }
   const double nx = sA == 0 ? -1.0 : (sA == 1 ? 1.0 : 0.0);
   const double ny = sA == 2 ? -1.0 : (sA == 3 ? 1.0 : 0.0);
-  const double zA = A.zf[((size_t)flc * 2 + 0) * S + al];
-  double zB = A.zf[((size_t)flc * 2 + 1) * S + al];
-  if (bnd) {
-    zB = zA;
-    if (bc == 0) {            // wall: mirror the normal discharge
-      const double qn = vA[1] * nx + vA[2] * ny;
-      vB[0] = vA[0];
-      vB[1] = vA[1] - 2.0 * qn * nx;
-      vB[2] = vA[2] - 2.0 * qn * ny;
-      vB[3] = vA[3];
-    } else if (bc == 1) {     // imposed elevation (tide), q extrapolated
-      const double tt = A.scal[1] + A.cstage * A.scal[0];
-      vB[0] = A.tide_amp * sin(6.283185307179586 * tt / A.tide_period + A.tide_phase);
-      vB[1] = vA[1];
-      vB[2] = vA[2];
-      vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? A.tide_cin : vA[3];
-    } else {                  // open: copy
-#pragma unroll
-      for (int q = 0; q < 4; ++q) vB[q] = vA[q];
-    }
-  }
   const double g = A.g, eps = A.eps;
-  const double sAw = vA[0] + zA, sBw = vB[0] + zB;
-  const double hA = sAw > 0.0 ? sAw : 0.0, hB = sBw > 0.0 ? sBw : 0.0;
-  const double ihA = inv_des(hA, eps), ihB = inv_des(hB, eps);
-  const double uxA = vA[1] * ihA, uyA = vA[2] * ihA, uxB = vB[1] * ihB, uyB = vB[2] * ihB;
-  const double unA = uxA * nx + uyA * ny, unB = uxB * nx + uyB * ny;
-  const double lA = fabs(unA) + sqrt(g * hA), lB = fabs(unB) + sqrt(g * hB);
-  const double lam = lA >= lB ? lA : lB;
-  const double zs = zA <= zB ? zA : zB;                       // z*_b = min(zb-, zb+)
-  const double tsA = vA[0] + zs, tsB = vB[0] + zs;
-  const double hsA = tsA > 0.0 ? tsA : 0.0, hsB = tsB > 0.0 ? tsB : 0.0;
-  const double qsxA = hsA * uxA, qsyA = hsA * uyA, qsxB = hsB * uxB, qsyB = hsB * uyB;
-  const double esA = vA[0] >= -zs ? vA[0] : -zs, esB = vB[0] >= -zs ? vB[0] : -zs;
-  const double mass = 0.5 * ((qsxA + qsxB) * nx + (qsyA + qsyB) * ny) + 0.5 * lam * (esA - esB);
-  const double momx = 0.5 * (qsxA * unA + qsxB * unB) + 0.5 * lam * (qsxA - qsxB);
-  const double momy = 0.5 * (qsyA * unA + qsyB * unB) + 0.5 * lam * (qsyA - qsyB);
-  const double pres = 0.5 * g * 0.5 * (hsA + hsB) * (esA - esB);
-  const double trac = 0.5 * ((qsxA * vA[3] + qsxB * vB[3]) * nx + (qsyA * vA[3] + qsyB * vB[3]) * ny) +
-                      0.5 * lam * (hsA * vA[3] - hsB * vB[3]);
   const double dxA = A.cdx[cA];
-  const double wl = act ? A.w[al] * dxA : 0.0;
-  const double cAv[4] = {-mass, -momx + pres * nx, -momy + pres * ny, -trac};
-  const double cBv[4] = {mass, momx + pres * nx, momy + pres * ny, trac};
-  // add the projections onto the face test functions of both sides into the
+  const double* tB0 = A.fl + (size_t)(sub < 0 ? 0 : 1 + sub) * S * N1;
+  const double tt = A.scal[1] + A.cstage * A.scal[0];
+  const double zeta_b = A.tide_amp * sin(6.283185307179586 * tt / A.tide_period + A.tide_phase);
+
+  double pA[NQ][N1], pB[NQ][N1];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) pA[q][k] = pB[q][k] = 0.0;
+  double lmax = 0.0;
+#pragma unroll 1
+  for (int al = lane; al < S; al += Q) {
+    double la[N1], lb[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      la[k] = A.fl[al * N1 + k];
+      lb[k] = tB0[al * N1 + k];
+    }
+    double vA[4] = {0.0, 0.0, 0.0, 0.0}, vB[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        sa += la[k] * cfA[q][k];
+        sb += lb[k] * cfB[q][k];
+      }
+      vA[q] = sa;
+      vB[q] = sb;
+    }
+    const double zA = A.zf[((size_t)flc * 2 + 0) * S + al];
+    double zB = A.zf[((size_t)flc * 2 + 1) * S + al];
+    if (bnd) {
+      zB = zA;
+      if (bc == 0) {            // wall: mirror the normal discharge
+        const double qn = vA[1] * nx + vA[2] * ny;
+        vB[0] = vA[0];
+        vB[1] = vA[1] - 2.0 * qn * nx;
+        vB[2] = vA[2] - 2.0 * qn * ny;
+        vB[3] = vA[3];
+      } else if (bc == 1) {     // imposed elevation (tide), q extrapolated
+        vB[0] = zeta_b;
+        vB[1] = vA[1];
+        vB[2] = vA[2];
+        vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? A.tide_cin : vA[3];
+      } else {                  // open: copy
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vB[q] = vA[q];
+      }
+    }
+    const double sAw = vA[0] + zA, sBw = vB[0] + zB;
+    const double hA = sAw > 0.0 ? sAw : 0.0, hB = sBw > 0.0 ? sBw : 0.0;
+    const double ihA = hA >= eps ? rcp_nr(hA) : inv_des(hA, eps);
+    const double ihB = hB >= eps ? rcp_nr(hB) : inv_des(hB, eps);
+    const double uxA = vA[1] * ihA, uyA = vA[2] * ihA, uxB = vB[1] * ihB, uyB = vB[2] * ihB;
+    const double unA = uxA * nx + uyA * ny, unB = uxB * nx + uyB * ny;
+    const double ghA = g * hA, ghB = g * hB;
+    const double lA = fabs(unA) + (ghA > 0.0 ? ghA * rsq_nr(ghA) : 0.0);
+    const double lB = fabs(unB) + (ghB > 0.0 ? ghB * rsq_nr(ghB) : 0.0);
+    const double lam = lA >= lB ? lA : lB;
+    const double zs = zA <= zB ? zA : zB;                       // z*_b = min(zb-, zb+)
+    const double tsA = vA[0] + zs, tsB = vB[0] + zs;
+    const double hsA = tsA > 0.0 ? tsA : 0.0, hsB = tsB > 0.0 ? tsB : 0.0;
+    const double qsxA = hsA * uxA, qsyA = hsA * uyA, qsxB = hsB * uxB, qsyB = hsB * uyB;
+    const double esA = vA[0] >= -zs ? vA[0] : -zs, esB = vB[0] >= -zs ? vB[0] : -zs;
+    const double mass = 0.5 * ((qsxA + qsxB) * nx + (qsyA + qsyB) * ny) + 0.5 * lam * (esA - esB);
+    const double momx = 0.5 * (qsxA * unA + qsxB * unB) + 0.5 * lam * (qsxA - qsxB);
+    const double momy = 0.5 * (qsyA * unA + qsyB * unB) + 0.5 * lam * (qsyA - qsyB);
+    const double pres = 0.5 * g * 0.5 * (hsA + hsB) * (esA - esB);
+    const double trac = 0.5 * ((qsxA * vA[3] + qsxB * vB[3]) * nx + (qsyA * vA[3] + qsyB * vB[3]) * ny) +
+                        0.5 * lam * (hsA * vA[3] - hsB * vB[3]);
+    const double wl = A.w[al] * dxA;
+    const double cAv[4] = {-mass, -momx + pres * nx, -momy + pres * ny, -trac};
+    const double cBv[4] = {mass, momx + pres * nx, momy + pres * ny, trac};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        pA[q][k] += wl * cAv[q] * la[k];
+        pB[q][k] += wl * cBv[q] * lb[k];
+      }
+    lmax = fmax(lmax, lam);
+  }
+  // finish the face integrals over the face's lanes and add them into the
   // residual slot; faces of one launch touch disjoint (cell, dof) sets
   const size_t KN = (size_t)A.K * NP;
   double* rA = A.res + (size_t)A.slot * 4 * KN + (size_t)cA * NP;
   double* rB = A.res + (size_t)A.slot * 4 * KN + (size_t)cB * NP;
-  const int nq = A.tracer ? 4 : 3;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q >= nq) break;
+  for (int q = 0; q < NQ; ++q) {
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const double va = gsum<P>(wl * cAv[q] * la[k]);
-      const double vb = gsum<P>(wl * cBv[q] * lb[k]);
+      const double va = gsum<Q>(pA[q][k]);
+      const double vb = gsum<Q>(pB[q][k]);
       const int ia = q * N1 + k;
-      if (fv && ok && (ia % P) == lane) rA[(size_t)q * KN + row_dof<R>(sA, k)] += va;
-      if (fv && ok && !bnd && ((ia + 2 * N1) % P) == lane) rB[(size_t)q * KN + row_dof<R>(sB, k)] += vb;
+      if (q < nq && act && (ia % Q) == lane) rA[(size_t)q * KN + row_dof<R>(sA, k)] += va;
+      if (q < nq && act && !bnd && ((ia + 1) % Q) == lane) rB[(size_t)q * KN + row_dof<R>(sB, k)] += vb;
     }
   }
   // positivity time-step bound (Prop. 3.2): w J_K / (lambda l_Gamma) on both sides
+  lmax = gmin<Q>(-lmax);
+  lmax = -lmax;
   double bnd_dt = 1e300;
-  if (act && lam > 0.0) {
-    bnd_dt = A.cw1[cA] * A.cdx[cA] * A.cdx[cA] / (lam * dxA);
-    if (!bnd) bnd_dt = fmin(bnd_dt, A.cw1[cB] * A.cdx[cB] * A.cdx[cB] / (lam * dxA));
+  if (act && lmax > 0.0) {
+    bnd_dt = A.cw1[cA] * A.cdx[cA] * A.cdx[cA] / (lmax * dxA);
+    if (!bnd) bnd_dt = fmin(bnd_dt, A.cw1[cB] * A.cdx[cB] * A.cdx[cB] / (lmax * dxA));
   }
   bnd_dt = gmin<kWave>(bnd_dt);
   if (tid == 0) A.bpart[A.bpart0 + blockIdx.x] = bnd_dt;
@@ -140,13 +169,9 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
 
 template <int R>
 static hipError_t face_r(int P, const FaceArgs& a, int nblk, hipStream_t s) {
-  switch (P) {
-    case 4: hipLaunchKernelGGL((k_face<R, 4>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_face<R, 8>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_face<R, 16>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_face<R, 32>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  (void)P;
+  if (a.tracer) hipLaunchKernelGGL((k_face<R, kFaceLanes, 4>), dim3(nblk), dim3(kWave), 0, s, a);
+  else hipLaunchKernelGGL((k_face<R, kFaceLanes, 3>), dim3(nblk), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 

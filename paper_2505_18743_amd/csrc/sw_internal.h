@@ -7,6 +7,7 @@
 namespace swk {
 
 constexpr int kWave = 64;
+constexpr int kFaceLanes = 4;   // lanes per face in the face kernel
 
 // ---- stage-kernel modes ---------------------------------------------------
 enum Mode : int {
@@ -28,6 +29,9 @@ struct LevelTabs {
   const double* mqinv;  // [NP][NP]     inverse exact mass matrix, unit square
   const double* meanw;  // [NP]         int psi_j over the unit square
   const double* fl;     // [3][S][N1]   l_k at face nodes: s, s/2, (1+s)/2
+  const double* dp;     // [S][N1]      l_k'(xhat_a) / dx
+  const double* wl;     // [S][N1]      w_a l_k(xhat_a)
+  const double* wdp;    // [S][N1]      w_a l_k'(xhat_a) / dx
   int S;
   double dx;
 };
