@@ -111,6 +111,68 @@ def cpu_baseline(name, seconds):
                        f"{el:.1f} s")
 
 
+def ensemble_bench(steps, warmup, device):
+    """64-member ensemble (uneven meshes, r in {1,2,3}): batched and graph-
+    replayed vs the same members as 64 contexts stepped one after another."""
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import member_solver, setup_ensemble
+    from workloads import workload
+    mem = workload("ensemble_64")
+    ens, inputs = setup_ensemble(mem, device)
+    stages = 3
+    dofs = sum(3 * (w["params"]["r"] + 1) ** 2 * len(w["mesh"]["level"]) for w in mem)
+    cells = sum(len(w["mesh"]["level"]) for w in mem)
+
+    def reset_ens():
+        for s, (bed, man, eta) in zip(ens.batches, inputs):
+            s.init_lake_at_rest(eta)
+            s.set_time(0.0)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    res = {}
+    for mode, graph in (("graph", True), ("eager", False)):
+        reset_ens()
+        ens.run(warmup, graph=graph)
+        ens.sync()
+        reset_ens()
+        ens.run(1, graph=graph)   # the first step after a reset is taken eagerly
+        ens.sync()
+        res[mode] = timed(lambda: ens.run(steps, graph=graph))
+        ens.sync()
+    ones = [member_solver(ens, inputs, mem, m, device) for m in range(len(mem))]
+    etas = []
+    for m in range(len(mem)):
+        b, i = ens.where[m]
+        etas.append(inputs[b][2][ens.batches[b].member_index(i)[2]])
+    for o in ones:
+        o.run(warmup)
+    for o, eta in zip(ones, etas):
+        o.init_lake_at_rest(eta)
+        o.set_time(0.0)
+        o.run(1)
+
+    def one_by_one():
+        for o in ones:
+            o.run(steps)
+    res["one_by_one"] = timed(one_by_one)
+    for o in ones:
+        o.close()
+    ens.close()
+    return dict(workload="ensemble_64", members=len(mem), cells=cells, dofs_per_stage=dofs, steps=steps,
+                value=dofs * stages * steps / res["graph"], unit="DoF-updates/s",
+                ms_per_step=res["graph"] / steps * 1e3, eager_ms_per_step=res["eager"] / steps * 1e3,
+                one_by_one_ms_per_step=res["one_by_one"] / steps * 1e3,
+                speedup_vs_one_by_one=res["one_by_one"] / res["graph"],
+                graph_speedup_vs_eager=res["eager"] / res["graph"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +181,7 @@ def main():
     ap.add_argument("--workload", default="beach_dambreak_256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ens-steps", type=int, default=300, help="ensemble_64 steps per mode (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -202,6 +265,8 @@ def main():
                 roofline=roof)
     line["config"]["max_newton_it"] = diag["max_newton_it"]
     line["config"]["r0_cells"] = diag["n_r0_cells"]
+    if args.ens_steps > 0:
+        line["ensemble"] = ensemble_bench(args.ens_steps, 3, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     else:

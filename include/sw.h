@@ -115,6 +115,25 @@ sw_status sw_create(sw_ctx **out, const sw_mesh_desc *mesh, const sw_params *p, 
 void sw_destroy(sw_ctx *c);
 const char *sw_last_error(void);
 
+/* Batched context of n_members independent problems (ensemble members; the
+ * paper treats one problem, this packs several into every kernel launch).
+ * meshes[m] and params[m] (host arrays of n_members) describe member m; the
+ * members may differ in mesh, cell size, boundary kinds, tide (tide_*) and
+ * CFL number (cfl), and must agree in r, rule, n_levels, S[0..n_levels), rk,
+ * g, eps, h_lim, eps0, newton_max, cfl_mode, tracer and adapt_degree
+ * (SW_EINVAL otherwise).  Each member has its own time, CFL time step (the
+ * minimum of Prop. 3.2's bound over its own faces) and diagnostics; faces
+ * join cells of one member only.  Cells are ordered by level, then member,
+ * then the member's own order; every array argument of the calls below uses
+ * that order (sw_cell_map gives it; for single-level members it is the
+ * members' cells one after the other).  A dt > 0 given to the step calls is
+ * used by every member.  sw_create(c, m, p, s) is sw_create_batch(c, 1, m, p, s). */
+sw_status sw_create_batch(sw_ctx **out, int32_t n_members, const sw_mesh_desc *meshes, const sw_params *params,
+                          void *stream);
+/* Host outputs [n_cells]: member of each cell and its index in that member's
+ * description (either may be NULL). */
+sw_status sw_cell_map(const sw_ctx *c, int32_t *member_host, int32_t *local_host);
+
 /* Sizes: cells, sample nodes (sum of S_L^2), nodal values per field. */
 sw_status sw_counts(const sw_ctx *c, int64_t *n_cells, int64_t *n_vol_nodes, int64_t *n_dofs);
 
@@ -163,8 +182,11 @@ sw_status sw_step_end(sw_ctx *c);
 sw_status sw_step(sw_ctx *c, double dt);
 sw_status sw_run(sw_ctx *c, int32_t n_steps, double dt);
 
-/* Diagnostics of the last step (host output).  Synchronises. */
+/* Diagnostics of the last step (host output).  Synchronises.  In a batched
+ * context dt and t are member 0's; masses and counts are summed, extrema
+ * taken over the members.  sw_member_diagnostics gives one member's. */
 sw_status sw_diagnostics(const sw_ctx *c, sw_diag *out_host);
+sw_status sw_member_diagnostics(const sw_ctx *c, int32_t member, sw_diag *out_host);
 /* Kernel timing.  With profiling on, each launch group of a kernel class is
  * bracketed by HIP events on the context's stream; sw_kernel_time returns the
  * accumulated milliseconds and kernel launches of one class (synchronises):
@@ -180,6 +202,30 @@ sw_status sw_kernel_time_reset(sw_ctx *c);
 
 /* Wait for the context's stream; reports SW_EDEVICE if a kernel flagged an error. */
 sw_status sw_sync(sw_ctx *c);
+
+/* ---- ensembles of independent members (not part of the paper's method) ----
+ * sw_ens_create groups the members into batched contexts (sw_create_batch),
+ * one per set of shared parameters listed there, in order of first appearance;
+ * the batches are created on `stream` (state I/O and setup calls on a batch use
+ * it) and stepped on streams of their own, forked from and joined back to
+ * `stream`, so that batches overlap on the device.  Errors as sw_create_batch. */
+typedef struct sw_ens sw_ens;
+sw_status sw_ens_create(sw_ens **out, int32_t n_members, const sw_mesh_desc *meshes, const sw_params *params,
+                        void *stream);
+void sw_ens_destroy(sw_ens *e);
+/* Number of batches; batch b's context (owned by the ensemble: do not destroy)
+ * and member count; batch and index inside the batch of member m. */
+sw_status sw_ens_batches(const sw_ens *e, int32_t *n_batches);
+sw_status sw_ens_batch(const sw_ens *e, int32_t b, sw_ctx **ctx, int32_t *n_members);
+sw_status sw_ens_member(const sw_ens *e, int32_t m, int32_t *batch, int32_t *index);
+/* n_steps steps of every member (dt > 0: that step for all, else each member's
+ * CFL step).  use_graph = 1: one step of all batches is captured once into a
+ * hipGraph (re-captured when dt changes) and replayed n times; a first step is
+ * taken eagerly when a batch has just been (re)initialised.  Results equal the
+ * eager path's bit for bit.  Work is enqueued on `stream`. */
+sw_status sw_ens_run(sw_ens *e, int32_t n_steps, double dt, int32_t use_graph);
+/* Wait for all work of the ensemble; SW_EDEVICE as sw_sync. */
+sw_status sw_ens_sync(sw_ens *e);
 
 #ifdef __cplusplus
 }

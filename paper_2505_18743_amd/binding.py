@@ -18,11 +18,13 @@ BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3}
 RULE = {"eq": 0, "gll": 1}
 RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3}
 
-EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_counts", "sw_node_coords", "sw_dof_coords",
-           "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset", "sw_set_state", "sw_get_state",
-           "sw_init_lake_at_rest", "sw_set_time", "sw_apply_operator", "sw_step_begin", "sw_rk_stage",
-           "sw_step_end", "sw_step", "sw_run", "sw_diagnostics", "sw_sync", "sw_profile", "sw_kernel_time",
-           "sw_kernel_time_reset"]
+EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_cell_map", "sw_counts",
+           "sw_node_coords", "sw_dof_coords", "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset",
+           "sw_set_state", "sw_get_state", "sw_init_lake_at_rest", "sw_set_time", "sw_apply_operator",
+           "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
+           "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
+           "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
+           "sw_ens_sync"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -63,6 +65,19 @@ def load():
     L = ctypes.CDLL(LIBPATH)
     vp = ctypes.c_void_p
     L.sw_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SwMeshDesc), ctypes.POINTER(SwParams), vp]
+    L.sw_create_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(SwMeshDesc),
+                                  ctypes.POINTER(SwParams), vp]
+    L.sw_cell_map.argtypes = [vp, vp, vp]
+    L.sw_member_diagnostics.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(SwDiag)]
+    L.sw_ens_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(SwMeshDesc),
+                                ctypes.POINTER(SwParams), vp]
+    L.sw_ens_destroy.argtypes = [vp]
+    L.sw_ens_destroy.restype = None
+    L.sw_ens_batches.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.sw_ens_batch.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int32)]
+    L.sw_ens_member.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.sw_ens_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
+    L.sw_ens_sync.argtypes = [vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
     L.sw_last_error.restype = ctypes.c_char_p
@@ -89,7 +104,7 @@ def load():
     L.sw_kernel_time.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.sw_kernel_time_reset.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("sw_destroy", "sw_last_error"):
+        if name not in ("sw_destroy", "sw_last_error", "sw_ens_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -128,42 +143,121 @@ def make_params(pd):
     return p
 
 
-class Solver:
-    """One context of the HIP library on one device and stream."""
+def make_mesh(mesh, keep):
+    """sw_mesh_desc of a mesh dict; the index arrays are appended to `keep`."""
+    lev = np.ascontiguousarray(mesh["level"], dtype=np.int32)
+    ii = np.ascontiguousarray(mesh["i"], dtype=np.int32)
+    jj = np.ascontiguousarray(mesh["j"], dtype=np.int32)
+    keep += [lev, ii, jj]
+    d = SwMeshDesc()
+    d.nx0, d.ny0 = int(mesh["nx0"]), int(mesh["ny0"])
+    d.x0, d.y0, d.dx0 = float(mesh["x0"]), float(mesh["y0"]), float(mesh["dx0"])
+    d.n_cells = len(lev)
+    d.level = lev.ctypes.data_as(_c_i32p)
+    d.i = ii.ctypes.data_as(_c_i32p)
+    d.j = jj.ctypes.data_as(_c_i32p)
+    for k, b in enumerate(mesh["bc"]):
+        d.bc[k] = BC[b]
+    return d
 
-    def __init__(self, mesh, params, device="cuda:0"):
+
+class Solver:
+    """One context of the HIP library on one device and stream.
+
+    `mesh` and `params` are one mesh dict and one parameter dict, or lists of
+    them (a batched context of independent members, sw_create_batch)."""
+
+    def __init__(self, mesh, params, device="cuda:0", _handle=None):
         L = load()
         self.dev = torch.device(device)
-        self.params = dict(params)
-        self._lev = np.ascontiguousarray(mesh["level"], dtype=np.int32)
-        self._i = np.ascontiguousarray(mesh["i"], dtype=np.int32)
-        self._j = np.ascontiguousarray(mesh["j"], dtype=np.int32)
-        d = SwMeshDesc()
-        d.nx0, d.ny0 = int(mesh["nx0"]), int(mesh["ny0"])
-        d.x0, d.y0, d.dx0 = float(mesh["x0"]), float(mesh["y0"]), float(mesh["dx0"])
-        d.n_cells = len(self._lev)
-        d.level = self._lev.ctypes.data_as(_c_i32p)
-        d.i = self._i.ctypes.data_as(_c_i32p)
-        d.j = self._j.ctypes.data_as(_c_i32p)
-        for k, b in enumerate(mesh["bc"]):
-            d.bc[k] = BC[b]
-        p = make_params(params)
+        batched = isinstance(mesh, (list, tuple))
+        meshes = list(mesh) if batched else [mesh]
+        plist = list(params) if batched else [params]
+        self.meshes, self.plist = meshes, plist
+        self.params = dict(plist[0])
+        self.n_members = len(meshes)
+        self._owned = _handle is None
         with torch.cuda.device(self.dev):
             self.stream = torch.cuda.current_stream(self.dev)
-            h = ctypes.c_void_p()
-            _check(L.sw_create(ctypes.byref(h), ctypes.byref(d), ctypes.byref(p),
-                               ctypes.c_void_p(self.stream.cuda_stream)), "sw_create")
+            if _handle is None:
+                keep = []
+                md = (SwMeshDesc * len(meshes))(*[make_mesh(m, keep) for m in meshes])
+                pp = (SwParams * len(plist))(*[make_params(q) for q in plist])
+                h = ctypes.c_void_p()
+                if batched:
+                    _check(L.sw_create_batch(ctypes.byref(h), len(meshes), md, pp,
+                                             ctypes.c_void_p(self.stream.cuda_stream)), "sw_create_batch")
+                else:
+                    _check(L.sw_create(ctypes.byref(h), md, pp, ctypes.c_void_p(self.stream.cuda_stream)),
+                           "sw_create")
+            else:
+                h = _handle
         self.h = h
         nc, nv, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(L.sw_counts(self.h, ctypes.byref(nc), ctypes.byref(nv), ctypes.byref(nd)), "sw_counts")
         self.n_cells, self.n_vol, self.n_dofs = nc.value, nv.value, nd.value
         self.np_ = self.n_dofs // self.n_cells
-        self.tracer = bool(params.get("tracer", False))
+        self.tracer = bool(self.params.get("tracer", False))
+        self._member_index = None
 
     def close(self):
         if getattr(self, "h", None):
-            load().sw_destroy(self.h)
+            if self._owned:
+                load().sw_destroy(self.h)
             self.h = None
+
+    # ---- members of a batched context ----
+    def cell_map(self):
+        """(member, index in the member's description) of every context cell."""
+        mem = np.zeros(self.n_cells, dtype=np.int32)
+        loc = np.zeros(self.n_cells, dtype=np.int32)
+        _check(load().sw_cell_map(self.h, mem.ctypes.data_as(ctypes.c_void_p), loc.ctypes.data_as(ctypes.c_void_p)),
+               "sw_cell_map")
+        return mem, loc
+
+    def member_index(self, m):
+        """Index arrays (cells, sample nodes, nodal values) of member m in
+        context order, listed in the member's own order."""
+        if self._member_index is None:
+            mem, loc = self.cell_map()
+            S = list(self.params["S"])
+            lev_ctx = np.empty(self.n_cells, dtype=np.int64)
+            for k in range(self.n_members):
+                sel = mem == k
+                lev_ctx[sel] = np.asarray(self.meshes[k]["level"])[loc[sel]]
+            nn = np.asarray(S, dtype=np.int64)[lev_ctx] ** 2
+            noff = np.concatenate([[0], np.cumsum(nn)])
+            out = []
+            for k in range(self.n_members):
+                cells = np.nonzero(mem == k)[0]
+                cells = cells[np.argsort(loc[cells], kind="stable")]
+                cnt = nn[cells]
+                start = np.repeat(noff[cells], cnt)
+                ofs = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+                nodes = start + ofs
+                dofs = (cells[:, None] * self.np_ + np.arange(self.np_)[None, :]).reshape(-1)
+                out.append((cells, nodes, dofs))
+            self._member_index = out
+        return self._member_index[m]
+
+    def gather_members(self, arrays, kind):
+        """Context-order tensor from per-member arrays (kind: 'cells', 'nodes' or 'dofs')."""
+        n = {"cells": self.n_cells, "nodes": self.n_vol, "dofs": self.n_dofs}[kind]
+        col = {"cells": 0, "nodes": 1, "dofs": 2}[kind]
+        full = torch.zeros(n, dtype=torch.float64, device=self.dev)
+        for m, a in enumerate(arrays):
+            idx = torch.as_tensor(self.member_index(m)[col], device=self.dev)
+            full[idx] = self._dev(a, idx.numel())
+        return full
+
+    def member_part(self, t, m, kind):
+        col = {"cells": 0, "nodes": 1, "dofs": 2}[kind]
+        return t[torch.as_tensor(self.member_index(m)[col], device=self.dev)]
+
+    def member_diagnostics(self, m):
+        d = SwDiag()
+        _check(load().sw_member_diagnostics(self.h, int(m), ctypes.byref(d)), "sw_member_diagnostics")
+        return {k: getattr(d, k) for k, _ in SwDiag._fields_}
 
     def __del__(self):
         try:
@@ -276,3 +370,94 @@ class Solver:
         d = SwDiag()
         _check(load().sw_diagnostics(self.h, ctypes.byref(d)), "sw_diagnostics")
         return {k: getattr(d, k) for k, _ in SwDiag._fields_}
+
+
+class Ensemble:
+    """Independent members grouped into batched contexts (sw_ens_create);
+    member arrays go in and out in each member's own layout."""
+
+    def __init__(self, meshes, params, device="cuda:0"):
+        L = load()
+        self.dev = torch.device(device)
+        self.meshes, self.plist = list(meshes), list(params)
+        self.n_members = len(self.meshes)
+        with torch.cuda.device(self.dev):
+            self.stream = torch.cuda.current_stream(self.dev)
+            keep = []
+            md = (SwMeshDesc * self.n_members)(*[make_mesh(m, keep) for m in self.meshes])
+            pp = (SwParams * self.n_members)(*[make_params(q) for q in self.plist])
+            h = ctypes.c_void_p()
+            _check(L.sw_ens_create(ctypes.byref(h), self.n_members, md, pp,
+                                   ctypes.c_void_p(self.stream.cuda_stream)), "sw_ens_create")
+        self.h = h
+        nb = ctypes.c_int32()
+        _check(L.sw_ens_batches(self.h, ctypes.byref(nb)), "sw_ens_batches")
+        self.where = []
+        for m in range(self.n_members):
+            b, i = ctypes.c_int32(), ctypes.c_int32()
+            _check(L.sw_ens_member(self.h, m, ctypes.byref(b), ctypes.byref(i)), "sw_ens_member")
+            self.where.append((b.value, i.value))
+        self.batches = []
+        for b in range(nb.value):
+            c, n = ctypes.c_void_p(), ctypes.c_int32()
+            _check(L.sw_ens_batch(self.h, b, ctypes.byref(c), ctypes.byref(n)), "sw_ens_batch")
+            mem = [m for m in range(self.n_members) if self.where[m][0] == b]
+            self.batches.append(Solver([self.meshes[m] for m in mem], [self.plist[m] for m in mem], device,
+                                       _handle=c))
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.batches:
+                s.h = None
+            load().sw_ens_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _per_batch(self, arrays):
+        out = [[] for _ in self.batches]
+        for m, a in enumerate(arrays):
+            out[self.where[m][0]].append(a)
+        return out
+
+    def member_coords(self, m, kind="nodes"):
+        b, i = self.where[m]
+        s = self.batches[b]
+        xy = s.node_coords() if kind == "nodes" else s.dof_coords()
+        col = 1 if kind == "nodes" else 2
+        return xy[s.member_index(i)[col]]
+
+    def set_bathymetry(self, arrays):
+        for s, arr in zip(self.batches, self._per_batch(arrays)):
+            s.set_bathymetry(s.gather_members(arr, "nodes"))
+
+    def set_manning(self, arrays):
+        for s, arr in zip(self.batches, self._per_batch(arrays)):
+            s.set_manning(s.gather_members(arr, "cells"))
+
+    def init_lake_at_rest(self, arrays):
+        for s, arr in zip(self.batches, self._per_batch(arrays)):
+            s.init_lake_at_rest(s.gather_members(arr, "dofs"))
+
+    def set_time(self, t):
+        for s in self.batches:
+            s.set_time(t)
+
+    def get_state(self, m):
+        b, i = self.where[m]
+        s = self.batches[b]
+        return [s.member_part(x, i, "dofs") for x in s.get_state()]
+
+    def member_diagnostics(self, m):
+        b, i = self.where[m]
+        return self.batches[b].member_diagnostics(i)
+
+    def run(self, n, dt=0.0, graph=True):
+        _check(load().sw_ens_run(self.h, int(n), float(dt), int(bool(graph))), "sw_ens_run")
+
+    def sync(self):
+        _check(load().sw_ens_sync(self.h), "sw_ens_sync")

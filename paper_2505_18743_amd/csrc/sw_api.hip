@@ -28,17 +28,18 @@ hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hi
 __global__ void k_bathy(const double*, const double*, double*, int, int, int, size_t);
 __global__ void k_facez(const int*, const int*, const int*, int, int, int, int, int, size_t, const double*,
                         const double*, const double*, double*, int*, int);
-__global__ void k_cellinit(LevelTabs, int, int, size_t, int, const double*, double*, double*);
+__global__ void k_cellinit(LevelTabs, int, int, size_t, int, const double*, const double*, double*, double*);
 __global__ void k_lake(LevelTabs, int, int, size_t, int, const double*, const double*, const double*, double*,
                        double*, double*);
-__global__ void k_set(double*, int, double);
 __global__ void k_fill(double*, size_t, double);
 __global__ void k_fill8(int8_t*, size_t, int8_t);
 __global__ void k_copy(const double*, double*, size_t);
-__global__ void k_minred(const double*, int, double*);
-__global__ void k_dt(const double*, int, double, double, double*);
-__global__ void k_diag_part(const double*, const int8_t*, int, double*);
-__global__ void k_diag(const double*, int, double*, double*);
+__global__ void k_fill_n(double*, int, double);
+__global__ void k_minred_seg(const double*, const int*, double*);
+__global__ void k_dt_seg(const double*, const int*, const double*, double*);
+__global__ void k_min_all(const double*, int, double*);
+__global__ void k_diag_part_seg(const double*, const int8_t*, const int*, double*);
+__global__ void k_diag_seg(const double*, const int*, double*, double*, const double*);
 
 hipError_t launch_elem_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
@@ -201,14 +202,14 @@ bool spd_inverse(std::vector<double>& A, int n) {
 
 struct LevelH {
   int L = 0, S = 0, P = 0;
-  double dx = 0, w1 = 0;
+  double w1 = 0;
   int cell0 = 0, ncell = 0;
   size_t off = 0;          // offset of this level's samples in the node arrays
   int face0 = 0, nface = 0;  // all faces whose fine (or equal) side is on this level
   size_t zfoff = 0;          // offset of this level's faces in the face-sample array
   // face classes: direction (x: W/E, y: S/N) x (conforming or boundary, sub-face 0,
   // sub-face 1); the faces of one class touch disjoint (cell, dof) sets
-  int cface0[6]{}, cnface[6]{}, cfblk0[6]{}, cfnblk[6]{};
+  int cface0[6]{}, cnface[6]{}, cfnblk[6]{};
   int nblk = 0;              // element-kernel blocks
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
@@ -221,21 +222,29 @@ struct sw_ctx {
   int dev = 0;
   hipStream_t s = nullptr;
   sw_params p{};
-  int r = 1, N1 = 2, NP = 4, K = 0, F = 0, ns = 3;
+  int r = 1, N1 = 2, NP = 4, K = 0, F = 0, ns = 3, M = 1;
   int64_t nvol = 0;
-  int nx0 = 0, ny0 = 0;
-  double x0 = 0, y0 = 0, dx0 = 0;
-  std::vector<int> lev, ci, cj;
+  // members: coarse-grid origin and cell size; per cell: member, index in the
+  // member's description, level, integer position, size
+  std::vector<double> mx0, my0, mdx0;
+  std::vector<int> cmem, cloc, lev, ci, cj;
+  std::vector<double> cdx;
   std::vector<LevelH> lv;
   double A[4][4]{}, b[4]{}, c[4]{};
-  int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr;
+  int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr, *d_cmem = nullptr;
   double *d_zb = nullptr, *d_braw = nullptr, *d_db = nullptr, *d_bvec = nullptr, *d_zmax = nullptr;
   double *d_nman = nullptr, *d_cdx = nullptr, *d_cw1 = nullptr, *d_zf = nullptr;
   double *d_sn[4]{}, *d_ss[4]{};
-  double *d_hn = nullptr, *d_cn = nullptr, *d_res = nullptr;
-  double *d_scal = nullptr, *d_cdiag = nullptr, *d_bpart = nullptr, *d_red = nullptr, *d_diag = nullptr;
+  double *d_hn = nullptr, *d_cn = nullptr, *d_res = nullptr, *d_cdiag = nullptr;
+  // per member: time, time step, time for sw_apply_operator, tide, CFL number,
+  // diagnostics [M][kMDiag], scratch
+  double *d_mt = nullptr, *d_mdt = nullptr, *d_mt_apply = nullptr, *d_mtide = nullptr, *d_mcfl = nullptr;
+  double *d_mdiag = nullptr, *d_mtmp = nullptr;
+  // segmented reductions: face chunks and cell chunks, grouped by member
+  double *d_fdt = nullptr, *d_part = nullptr;
+  int *d_fch = nullptr, *d_fch_m0 = nullptr, *d_cch = nullptr, *d_cch_m0 = nullptr;
+  int nfch = 0, ncch = 0;
   int8_t *d_flag = nullptr, *d_allwet = nullptr, *d_need = nullptr;
-  int fblk_total = 0;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
   bool fixed_dt = false;
   bool bathy_set = false;
@@ -293,6 +302,8 @@ namespace {
 
 constexpr int kNSlot = 5;   // residual slots: up to 4 stages + one for sw_apply_operator
 constexpr int kApplySlot = 4;
+constexpr int kMDiag = 16;  // per-member diagnostics: D_* slots, [7] dt, [8] t
+constexpr int kFaceChunk = 1024, kCellChunk = 256;
 
 void tableau(int rk, int& s, double A[4][4], double b[4], double c[4]) {
   for (int i = 0; i < 4; ++i) {
@@ -341,6 +352,30 @@ void tableau(int rk, int& s, double A[4][4], double b[4], double c[4]) {
 
 int64_t key(int L, int i, int j) { return ((int64_t)L << 52) | ((int64_t)i << 26) | (int64_t)j; }
 
+// Split [0, n) into chunks of at most `cap` items that do not cross a change of
+// member; chunks are listed member by member.  Output: chunk (begin, length)
+// pairs and the first chunk of every member (m0[M] = number of chunks).
+void make_chunks(const std::vector<int>& mem_of, int M, int cap, std::vector<int>& ch, std::vector<int>& m0) {
+  std::vector<std::vector<int>> per(M);
+  const int n = (int)mem_of.size();
+  int i = 0;
+  while (i < n) {
+    const int m = mem_of[i];
+    int j = i + 1;
+    while (j < n && j - i < cap && mem_of[j] == m) ++j;
+    per[m].push_back(i);
+    per[m].push_back(j - i);
+    i = j;
+  }
+  ch.clear();
+  m0.assign(M + 1, 0);
+  for (int m = 0; m < M; ++m) {
+    m0[m] = (int)ch.size() / 2;
+    ch.insert(ch.end(), per[m].begin(), per[m].end());
+  }
+  m0[M] = (int)ch.size() / 2;
+}
+
 sw_status build_tables(sw_ctx* c, LevelH& L) {
   const int S = L.S, N1 = c->N1, NP = c->NP;
   if (c->p.rule == SW_RULE_EQ) eqr(S, L.xh, L.wh);
@@ -350,8 +385,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   std::vector<double> tab;
   const size_t o_w = 0, o_l = o_w + S, o_d = o_l + (size_t)S * N1, o_m0 = o_d + (size_t)S * N1,
                o_mq = o_m0 + (size_t)NP * NP, o_mean = o_mq + (size_t)NP * NP, o_fl = o_mean + NP,
-               o_dp = o_fl + (size_t)3 * S * N1, o_wl = o_dp + (size_t)S * N1, o_wdp = o_wl + (size_t)S * N1,
-               total = o_wdp + (size_t)S * N1;
+               o_wl = o_fl + (size_t)3 * S * N1, o_wd = o_wl + (size_t)S * N1, total = o_wd + (size_t)S * N1;
   tab.assign(total, 0.0);
   for (int a = 0; a < S; ++a) {
     tab[o_w + a] = L.wh[a];
@@ -361,9 +395,8 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
       tab[o_fl + (0 * S + a) * N1 + k] = lag(xi, k, L.xh[a]);
       tab[o_fl + (1 * S + a) * N1 + k] = lag(xi, k, 0.5 * L.xh[a]);
       tab[o_fl + (2 * S + a) * N1 + k] = lag(xi, k, 0.5 * (1.0 + L.xh[a]));
-      tab[o_dp + a * N1 + k] = dlag(xi, k, L.xh[a]) / L.dx;
       tab[o_wl + a * N1 + k] = L.wh[a] * lag(xi, k, L.xh[a]);
-      tab[o_wdp + a * N1 + k] = L.wh[a] * dlag(xi, k, L.xh[a]) / L.dx;
+      tab[o_wd + a * N1 + k] = L.wh[a] * dlag(xi, k, L.xh[a]);
     }
   }
   // all-wet mass matrix of the sample rule on the unit square, and its inverse
@@ -412,11 +445,9 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.mqinv = L.d_tab + o_mq;
   L.tabs.meanw = L.d_tab + o_mean;
   L.tabs.fl = L.d_tab + o_fl;
-  L.tabs.dp = L.d_tab + o_dp;
   L.tabs.wl = L.d_tab + o_wl;
-  L.tabs.wdp = L.d_tab + o_wdp;
+  L.tabs.wd = L.d_tab + o_wd;
   L.tabs.S = S;
-  L.tabs.dx = L.dx;
   L.w1 = L.wh[0];
   return SW_OK;
 }
@@ -436,6 +467,9 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.bvec = c->d_bvec;
   a.zmax = c->d_zmax;
   a.nman = c->d_nman;
+  a.cdx = c->d_cdx;
+  a.cmem = c->d_cmem;
+  a.mdt = c->d_mdt;
   for (int f = 0; f < 4; ++f) {
     a.sn[f] = c->d_sn[f];
     a.ss[f] = c->d_ss[f];
@@ -450,7 +484,6 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.cdiag = c->d_cdiag;
   a.diag_init = 0;
   a.allwet = c->d_allwet;
-  a.scal = c->d_scal;
   a.err = c->d_err;
   a.slot = 0;
   a.nterm = 0;
@@ -480,25 +513,23 @@ FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st,
   a.slot = slot;
   a.cdx = c->d_cdx;
   a.cw1 = c->d_cw1;
+  a.cmem = c->d_cmem;
   a.fl = L.tabs.fl;
   a.w = L.tabs.w;
-  a.scal = c->d_scal;
+  a.mt = c->d_mt;
+  a.mdt = c->d_mdt;
+  a.mtide = c->d_mtide;
   a.cstage = cstage;
-  a.bpart = c->d_bpart;
-  a.bpart0 = L.cfblk0[cls];
+  a.fdt = c->d_fdt;
   a.err = c->d_err;
   a.g = c->p.g;
   a.eps = c->p.eps;
   a.tracer = c->p.tracer ? 1 : 0;
-  a.tide_amp = c->p.tide_amp;
-  a.tide_period = c->p.tide_period;
-  a.tide_phase = c->p.tide_phase;
-  a.tide_cin = c->p.tide_c_in;
   return a;
 }
 
 // all face classes of all levels, adding into residual slot `slot`
-sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, const double* scal_override = nullptr) {
+sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, const double* mt_override = nullptr) {
   int n = 0;
   for (auto& L : c->lv)
     for (int k = 0; k < 6; ++k) n += L.cnface[k] > 0;
@@ -507,19 +538,20 @@ sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, con
     for (int k = 0; k < 6; ++k) {
       if (L.cnface[k] == 0) continue;
       FaceArgs fa = face_args(c, L, k, st, cstage, slot);
-      if (scal_override) fa.scal = scal_override;
+      if (mt_override) fa.mt = mt_override;
       HIPCHK(launch_face(c->r, L.P, fa, L.cfnblk[k], c->s));
     }
   return SW_OK;
 }
 
-// dt = cfl * min of the face kernels' block bounds (two-level reduction)
-sw_status reduce_dt(sw_ctx* c, double cfl, double* dst) {
-  if (c->fblk_total == 0) return SW_OK;
-  const int n1 = (c->fblk_total + 1023) / 1024;
-  hipLaunchKernelGGL(k_minred, dim3(n1), dim3(256), 0, c->s, c->d_bpart, c->fblk_total, c->d_red);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, c->s, c->d_red, n1, cfl, 0.0, dst);
+// per-member dt = cfl_m * min of the member's face bounds (two-level segmented
+// reduction; mcfl == nullptr gives the bare bound)
+sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
+  if (c->nfch > 0) {
+    hipLaunchKernelGGL(k_minred_seg, dim3(c->nfch), dim3(256), 0, c->s, c->d_fdt, c->d_fch, c->d_part);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_dt_seg, dim3(c->M), dim3(256), 0, c->s, c->d_part, c->d_fch_m0, mcfl, dst);
   HIPCHK(hipGetLastError());
   return SW_OK;
 }
@@ -575,7 +607,7 @@ sw_status rebake(sw_ctx* c) {
     if (L.ncell > 0) {
       const int n = L.ncell * c->NP;
       hipLaunchKernelGGL(k_cellinit, dim3((n + 127) / 128), dim3(128), 0, c->s, L.tabs, L.cell0, L.ncell, L.off,
-                         c->N1, c->d_zb, c->d_bvec, c->d_zmax);
+                         c->N1, c->d_zb, c->d_cdx, c->d_bvec, c->d_zmax);
       HIPCHK(hipGetLastError());
     }
   }
@@ -593,112 +625,135 @@ extern "C" {
 
 const char* sw_last_error(void) { return g_err.c_str(); }
 
-sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, void* stream) {
-  if (!out || !m || !p) return fail(SW_EINVAL, "NULL argument to sw_create");
+sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* meshes, const sw_params* params,
+                          void* stream) {
+  if (!out || !meshes || !params) return fail(SW_EINVAL, "NULL argument to sw_create_batch");
   *out = nullptr;
+  if (n_members < 1) return fail(SW_EINVAL, "n_members must be >= 1");
+  const sw_params* p = &params[0];
   if (p->r < 1 || p->r > 3) return fail(SW_EINVAL, "r must be 1, 2 or 3");
   if (p->rule != SW_RULE_EQ && p->rule != SW_RULE_GLL) return fail(SW_EINVAL, "unknown rule");
   if (p->rk < SW_RK_FE || p->rk > SW_RK_RK44) return fail(SW_EINVAL, "unknown RK scheme");
   if (!(p->eps > 0.0)) return fail(SW_EINVAL, "eps must be > 0");
   if (p->newton_max < 1 || p->newton_max > 1000) return fail(SW_EINVAL, "newton_max out of range");
-  if (p->tide_period == 0.0 && (m->bc[0] == SW_BC_ELEV || m->bc[1] == SW_BC_ELEV || m->bc[2] == SW_BC_ELEV ||
-                                m->bc[3] == SW_BC_ELEV))
-    return fail(SW_EINVAL, "tide_period must be non-zero with an elevation boundary");
-  if (m->n_cells < 1 || !m->level || !m->i || !m->j) return fail(SW_EINVAL, "empty mesh");
-  if (m->nx0 < 1 || m->ny0 < 1 || !(m->dx0 > 0.0)) return fail(SW_EINVAL, "bad coarse grid");
-  for (int s = 0; s < 4; ++s)
-    if (m->bc[s] < 0 || m->bc[s] > 3) return fail(SW_EINVAL, "bad boundary kind");
-  if ((m->bc[0] == SW_BC_PERIODIC) != (m->bc[1] == SW_BC_PERIODIC) ||
-      (m->bc[2] == SW_BC_PERIODIC) != (m->bc[3] == SW_BC_PERIODIC))
-    return fail(SW_EINVAL, "periodic boundaries must come in pairs");
+  if (p->n_levels < 1 || p->n_levels > 8) return fail(SW_EINVAL, "n_levels must be 1..8");
+  for (int m = 0; m < n_members; ++m) {
+    const sw_params& q = params[m];
+    bool same = q.r == p->r && q.rule == p->rule && q.rk == p->rk && q.n_levels == p->n_levels && q.g == p->g &&
+                q.eps == p->eps && q.h_lim == p->h_lim && q.eps0 == p->eps0 && q.newton_max == p->newton_max &&
+                q.cfl_mode == p->cfl_mode && (q.tracer != 0) == (p->tracer != 0) &&
+                (q.adapt_degree != 0) == (p->adapt_degree != 0);
+    for (int L = 0; L < p->n_levels; ++L) same = same && q.S[L] == p->S[L];
+    if (!same)
+      return fail(SW_EINVAL, "member " + std::to_string(m) +
+                                 ": members of one batch must share r, rule, rk, S, g, eps, h_lim, eps0, newton_max, "
+                                 "cfl_mode, tracer and adapt_degree");
+    const sw_mesh_desc& md = meshes[m];
+    const bool elev = md.bc[0] == SW_BC_ELEV || md.bc[1] == SW_BC_ELEV || md.bc[2] == SW_BC_ELEV ||
+                      md.bc[3] == SW_BC_ELEV;
+    if (q.tide_period == 0.0 && elev)
+      return fail(SW_EINVAL, "tide_period must be non-zero with an elevation boundary");
+    if (md.n_cells < 1 || !md.level || !md.i || !md.j) return fail(SW_EINVAL, "empty mesh");
+    if (md.nx0 < 1 || md.ny0 < 1 || !(md.dx0 > 0.0)) return fail(SW_EINVAL, "bad coarse grid");
+    for (int sd = 0; sd < 4; ++sd)
+      if (md.bc[sd] < 0 || md.bc[sd] > 3) return fail(SW_EINVAL, "bad boundary kind");
+    if ((md.bc[0] == SW_BC_PERIODIC) != (md.bc[1] == SW_BC_PERIODIC) ||
+        (md.bc[2] == SW_BC_PERIODIC) != (md.bc[3] == SW_BC_PERIODIC))
+      return fail(SW_EINVAL, "periodic boundaries must come in pairs");
+  }
   auto* c = new sw_ctx();
+  auto bail = [&](sw_status st, const std::string& msg) {
+    delete c;
+    return fail(st, msg);
+  };
   c->s = (hipStream_t)stream;
-  HIPCHK(hipGetDevice(&c->dev));
+  {
+    hipError_t e = hipGetDevice(&c->dev);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
   c->p = *p;
+  c->M = n_members;
   c->r = p->r;
   c->N1 = p->r + 1;
   c->NP = c->N1 * c->N1;
-  c->K = m->n_cells;
-  c->nx0 = m->nx0;
-  c->ny0 = m->ny0;
-  c->x0 = m->x0;
-  c->y0 = m->y0;
-  c->dx0 = m->dx0;
   tableau(p->rk, c->ns, c->A, c->b, c->c);
-  const int K = c->K;
-  c->lev.assign(m->level, m->level + K);
-  c->ci.assign(m->i, m->i + K);
-  c->cj.assign(m->j, m->j + K);
+  const int M = n_members;
+  // per-member validation: level order, extent, tiling, duplicates
   int maxL = 0;
-  for (int k = 0; k < K; ++k) {
-    const int L = c->lev[k];
-    if (L < 0 || L >= 8 || L >= p->n_levels) {
-      delete c;
-      return fail(SW_EINVAL, "cell level out of range (n_levels)");
-    }
-    if (k > 0 && L < c->lev[k - 1]) {
-      delete c;
-      return fail(SW_EINVAL, "cells must be sorted by level");
-    }
-    if (c->ci[k] < 0 || c->cj[k] < 0 || c->ci[k] >= (m->nx0 << L) || c->cj[k] >= (m->ny0 << L)) {
-      delete c;
-      return fail(SW_EINVAL, "cell outside the domain");
-    }
-    maxL = std::max(maxL, L);
-  }
-  // tiling check: sum of areas (in finest units) equals the domain
-  {
+  int64_t Ktot = 0;
+  std::vector<std::unordered_map<int64_t, int>> leaf(M);
+  for (int m = 0; m < M; ++m) {
+    const sw_mesh_desc& md = meshes[m];
+    c->mx0.push_back(md.x0);
+    c->my0.push_back(md.y0);
+    c->mdx0.push_back(md.dx0);
     long double area = 0.0L;
-    for (int k = 0; k < K; ++k) area += std::ldexp(1.0L, -2 * c->lev[k]);
-    if (std::fabs((double)(area - (long double)m->nx0 * m->ny0)) > 1e-9) {
-      delete c;
-      return fail(SW_EINVAL, "cells do not tile the domain");
+    leaf[m].reserve((size_t)md.n_cells * 2);
+    for (int k = 0; k < md.n_cells; ++k) {
+      const int L = md.level[k];
+      if (L < 0 || L >= p->n_levels) return bail(SW_EINVAL, "cell level out of range (n_levels)");
+      if (k > 0 && L < md.level[k - 1]) return bail(SW_EINVAL, "cells must be sorted by level");
+      if (md.i[k] < 0 || md.j[k] < 0 || md.i[k] >= (md.nx0 << L) || md.j[k] >= (md.ny0 << L))
+        return bail(SW_EINVAL, "cell outside the domain");
+      maxL = std::max(maxL, L);
+      area += std::ldexp(1.0L, -2 * L);
+      if (!leaf[m].emplace(key(L, md.i[k], md.j[k]), k).second) return bail(SW_EINVAL, "duplicate cell");
     }
+    if (std::fabs((double)(area - (long double)md.nx0 * md.ny0)) > 1e-9)
+      return bail(SW_EINVAL, "cells do not tile the domain");
+    Ktot += md.n_cells;
   }
-  std::unordered_map<int64_t, int> leaf;
-  leaf.reserve(K * 2);
-  for (int k = 0; k < K; ++k) {
-    if (!leaf.emplace(key(c->lev[k], c->ci[k], c->cj[k]), k).second) {
-      delete c;
-      return fail(SW_EINVAL, "duplicate cell");
-    }
-  }
-  // levels
+  if (Ktot > (int64_t)1 << 30) return bail(SW_EINVAL, "too many cells");
+  c->K = (int)Ktot;
+  const int K = c->K;
+  // levels (sample counts shared by the members)
   for (int L = 0; L <= maxL; ++L) {
     LevelH h;
     h.L = L;
     h.S = p->S[L];
-    if (h.S < p->r + 2 || h.S > 32) {
-      delete c;
-      return fail(SW_EINVAL, "S must satisfy r+2 <= S <= 32 on every level");
-    }
+    if (h.S < p->r + 2 || h.S > 32) return bail(SW_EINVAL, "S must satisfy r+2 <= S <= 32 on every level");
     h.P = lanes_for(h.S);
-    h.dx = m->dx0 / std::ldexp(1.0, L);
     c->lv.push_back(h);
   }
+  // context order: level, then member, then the member's own order
+  std::vector<std::vector<int>> ctx_of(M);
+  for (int m = 0; m < M; ++m) ctx_of[m].assign(meshes[m].n_cells, -1);
   {
-    int k = 0;
     int64_t off = 0;
     for (auto& L : c->lv) {
-      L.cell0 = k;
-      while (k < K && c->lev[k] == L.L) ++k;
-      L.ncell = k - L.cell0;
+      L.cell0 = (int)c->cmem.size();
+      for (int m = 0; m < M; ++m) {
+        const sw_mesh_desc& md = meshes[m];
+        for (int k = 0; k < md.n_cells; ++k) {
+          if (md.level[k] != L.L) continue;
+          ctx_of[m][k] = (int)c->cmem.size();
+          c->cmem.push_back(m);
+          c->cloc.push_back(k);
+          c->lev.push_back(L.L);
+          c->ci.push_back(md.i[k]);
+          c->cj.push_back(md.j[k]);
+          c->cdx.push_back(md.dx0 / std::ldexp(1.0, L.L));
+        }
+      }
+      L.ncell = (int)c->cmem.size() - L.cell0;
       L.off = (size_t)off;
       off += (int64_t)L.ncell * L.S * L.S;
     }
     c->nvol = off;
   }
   // faces: conforming (recorded from the W/S cell), hanging (from the fine cell),
-  // boundary; A is the fine or equal side
+  // boundary; A is the fine or equal side.  Faces join cells of one member only.
   struct FaceH { int a, b, sa, sb, sub, bnd, bc, lvl; };
   std::vector<FaceH> fh;
-  const bool perx = m->bc[0] == SW_BC_PERIODIC, pery = m->bc[2] == SW_BC_PERIODIC;
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1}, opp[4] = {1, 0, 3, 2};
   for (int k = 0; k < K; ++k) {
+    const int m = c->cmem[k];
+    const sw_mesh_desc& md = meshes[m];
+    const bool perx = md.bc[0] == SW_BC_PERIODIC, pery = md.bc[2] == SW_BC_PERIODIC;
     const int L = c->lev[k], i = c->ci[k], j = c->cj[k];
-    const int nxL = m->nx0 << L, nyL = m->ny0 << L;
-    for (int s = 0; s < 4; ++s) {
-      int ni = i + di[s], nj = j + dj[s];
+    const int nxL = md.nx0 << L, nyL = md.ny0 << L;
+    for (int sd = 0; sd < 4; ++sd) {
+      int ni = i + di[sd], nj = j + dj[sd];
       bool outside = false;
       if (ni < 0 || ni >= nxL) {
         if (perx) ni = (ni + nxL) % nxL;
@@ -709,19 +764,19 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
         else outside = true;
       }
       if (outside) {
-        fh.push_back({k, -1, s, 0, -1, 1, m->bc[s], L});
+        fh.push_back({k, -1, sd, 0, -1, 1, md.bc[sd], L});
         continue;
       }
-      auto it = leaf.find(key(L, ni, nj));
-      if (it != leaf.end()) {
-        if (s == 1 || s == 3) fh.push_back({k, it->second, s, opp[s], -1, 0, 0, L});
+      auto it = leaf[m].find(key(L, ni, nj));
+      if (it != leaf[m].end()) {
+        if (sd == 1 || sd == 3) fh.push_back({k, ctx_of[m][it->second], sd, opp[sd], -1, 0, 0, L});
         continue;
       }
       if (L > 0) {
-        auto ic = leaf.find(key(L - 1, ni >> 1, nj >> 1));
-        if (ic != leaf.end()) {
-          const int sub = (s < 2) ? (j & 1) : (i & 1);
-          fh.push_back({k, ic->second, s, opp[s], sub, 0, 0, L});
+        auto ic = leaf[m].find(key(L - 1, ni >> 1, nj >> 1));
+        if (ic != leaf[m].end()) {
+          const int sub = (sd < 2) ? (j & 1) : (i & 1);
+          fh.push_back({k, ctx_of[m][ic->second], sd, opp[sd], sub, 0, 0, L});
           continue;
         }
       }
@@ -729,47 +784,50 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
       bool ok = true;
       for (int t = 0; t < 2; ++t) {
         int ki, kj;
-        if (s < 2) {
-          ki = 2 * ni + (s == 0 ? 1 : 0);
+        if (sd < 2) {
+          ki = 2 * ni + (sd == 0 ? 1 : 0);
           kj = 2 * nj + t;
         } else {
           ki = 2 * ni + t;
-          kj = 2 * nj + (s == 2 ? 1 : 0);
+          kj = 2 * nj + (sd == 2 ? 1 : 0);
         }
-        if (leaf.find(key(L + 1, ki, kj)) == leaf.end()) ok = false;
+        if (leaf[m].find(key(L + 1, ki, kj)) == leaf[m].end()) ok = false;
       }
-      if (!ok) {
-        delete c;
-        return fail(SW_EINVAL, "mesh is not 2:1 balanced at cell " + std::to_string(k));
-      }
+      if (!ok)
+        return bail(SW_EINVAL, "mesh is not 2:1 balanced at cell " + std::to_string(c->cloc[k]) + " of member " +
+                                   std::to_string(m));
     }
   }
-  // class of a face: x or y direction times (conforming/boundary, sub-face 0, sub-face 1)
+  // class of a face: x or y direction times (conforming/boundary, sub-face 0, sub-face 1);
+  // the stable sort keeps the faces of a class grouped by member
   auto cls = [](const FaceH& h) { return (h.sa < 2 ? 0 : 3) + (h.sub + 1); };
   std::stable_sort(fh.begin(), fh.end(), [&](const FaceH& x, const FaceH& y) {
     return x.lvl != y.lvl ? x.lvl < y.lvl : cls(x) < cls(y);
   });
   c->F = (int)fh.size();
-  std::vector<int> fA(c->F), fB(c->F), meta(c->F), used((size_t)K * 8, 0);
+  std::vector<int> fA(c->F), fB(c->F), meta(c->F), used((size_t)K * 8, 0), fmem(c->F);
   for (int f = 0; f < c->F; ++f) {
     const FaceH& h = fh[f];
     fA[f] = h.a;
     fB[f] = h.b;
+    fmem[f] = c->cmem[h.a];
     meta[f] = h.sa | (h.sb << 2) | ((h.sub + 1) << 4) | (h.bnd << 6) | (h.bc << 8);
     // every cell side carries one face, or two sub-faces on a coarse side
-    if (used[(size_t)h.a * 8 + h.sa * 2]++) {
-      delete c;
-      return fail(SW_EINVAL, "two faces on one cell side");
-    }
-    if (!h.bnd && used[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)]++) {
-      delete c;
-      return fail(SW_EINVAL, "two faces on one cell side");
-    }
+    if (used[(size_t)h.a * 8 + h.sa * 2]++) return bail(SW_EINVAL, "two faces on one cell side");
+    if (!h.bnd && used[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)]++)
+      return bail(SW_EINVAL, "two faces on one cell side");
   }
+  // chunks of the segmented reductions (faces: dt bounds; cells: diagnostics)
+  std::vector<int> fch, fch_m0, cch, cch_m0;
+  {
+    make_chunks(fmem, M, kFaceChunk, fch, fch_m0);
+    make_chunks(c->cmem, M, kCellChunk, cch, cch_m0);
+    c->nfch = (int)fch.size() / 2;
+    c->ncch = (int)cch.size() / 2;
+  }
+  size_t zo = 0;
   {
     int f = 0;
-    size_t zo = 0;
-    int fblk = 0;
     for (auto& L : c->lv) {
       L.face0 = f;
       const int cpb = kWave / L.P;
@@ -778,30 +836,27 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
         while (f < c->F && fh[f].lvl == L.L && cls(fh[f]) == k) ++f;
         L.cnface[k] = f - L.cface0[k];
         L.cfnblk[k] = (L.cnface[k] + kWave / kFaceLanes - 1) / (kWave / kFaceLanes);
-        L.cfblk0[k] = fblk;
-        fblk += L.cfnblk[k];
       }
       L.nface = f - L.face0;
       L.zfoff = zo;
       zo += (size_t)L.nface * 2 * L.S;
       L.nblk = (L.ncell + cpb - 1) / cpb;
     }
-    if (f != c->F) {
-      delete c;
-      return fail(SW_EINVAL, "internal: face classes do not cover the face list");
-    }
-    c->fblk_total = fblk;
+    if (f != c->F) return bail(SW_EINVAL, "internal: face classes do not cover the face list");
+  }
+  {
     sw_status st = SW_OK;
     const size_t KN = (size_t)K * c->NP;
-#define ALLOC(ptr, n)                \
-  if ((st = c->alloc(&ptr, n)) != SW_OK) { \
-    delete c;                        \
-    return st;                       \
+#define ALLOC(ptr, n)                          \
+  if ((st = c->alloc(&ptr, n)) != SW_OK) {     \
+    delete c;                                  \
+    return st;                                 \
   }
     ALLOC(c->d_fA, c->F);
     ALLOC(c->d_fB, c->F);
     ALLOC(c->d_meta, c->F);
     ALLOC(c->d_err, 1);
+    ALLOC(c->d_cmem, K);
     ALLOC(c->d_zb, (size_t)c->nvol);
     ALLOC(c->d_braw, (size_t)c->nvol);
     ALLOC(c->d_db, K);
@@ -818,12 +873,21 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
     ALLOC(c->d_hn, KN);
     ALLOC(c->d_cn, KN);
     ALLOC(c->d_res, (size_t)kNSlot * 4 * KN);
-    ALLOC(c->d_scal, 8);
     ALLOC(c->d_cdiag, (size_t)K * D_NSLOT);
-    ALLOC(c->d_bpart, (size_t)std::max(c->fblk_total, 1));
-    ALLOC(c->d_red, (size_t)std::max((c->fblk_total + 1023) / 1024, (K + 255) / 256) * D_NSLOT);
+    ALLOC(c->d_mt, M);
+    ALLOC(c->d_mdt, M);
+    ALLOC(c->d_mt_apply, M);
+    ALLOC(c->d_mtide, (size_t)4 * M);
+    ALLOC(c->d_mcfl, M);
+    ALLOC(c->d_mdiag, (size_t)kMDiag * M);
+    ALLOC(c->d_mtmp, M);
+    ALLOC(c->d_fdt, c->F);
+    ALLOC(c->d_part, (size_t)std::max(c->nfch, c->ncch) * D_NSLOT);
+    ALLOC(c->d_fch, fch.size());
+    ALLOC(c->d_fch_m0, M + 1);
+    ALLOC(c->d_cch, cch.size());
+    ALLOC(c->d_cch_m0, M + 1);
     ALLOC(c->d_need, K);
-    ALLOC(c->d_diag, 16);
     ALLOC(c->d_flag, K);
     ALLOC(c->d_allwet, K);
 #undef ALLOC
@@ -835,36 +899,67 @@ sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, voi
       return st;
     }
   }
-  std::vector<double> cdx(K), cw1(K);
-  for (int k = 0; k < K; ++k) {
-    const LevelH& L = c->lv[c->lev[k]];
-    cdx[k] = L.dx;
-    cw1[k] = p->cfl_mode == 1 ? L.w1 : 1.0;
+  std::vector<double> cw1(K), mtide(4 * (size_t)M), mcfl(M);
+  for (int k = 0; k < K; ++k) cw1[k] = p->cfl_mode == 1 ? c->lv[c->lev[k]].w1 : 1.0;
+  for (int m = 0; m < M; ++m) {
+    mtide[4 * m + 0] = params[m].tide_amp;
+    mtide[4 * m + 1] = params[m].tide_period;
+    mtide[4 * m + 2] = params[m].tide_phase;
+    mtide[4 * m + 3] = params[m].tide_c_in;
+    mcfl[m] = params[m].cfl;
   }
-  HIPCHK(hipMemcpy(c->d_fA, fA.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_fB, fB.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_meta, meta.data(), sizeof(int) * c->F, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_cdx, cdx.data(), sizeof(double) * K, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_cw1, cw1.data(), sizeof(double) * K, hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(c->d_err, 0, sizeof(int)));
-  HIPCHK(hipMemset(c->d_db, 0, sizeof(double) * K));
-  HIPCHK(hipMemset(c->d_nman, 0, sizeof(double) * K));
-  HIPCHK(hipMemset(c->d_scal, 0, sizeof(double) * 8));
-  HIPCHK(hipMemset(c->d_diag, 0, sizeof(double) * 16));
-  HIPCHK(hipMemset(c->d_cdiag, 0, sizeof(double) * (size_t)K * D_NSLOT));
-  HIPCHK(hipMemset(c->d_need, 0, K));
-  HIPCHK(hipMemset(c->d_res, 0, sizeof(double) * (size_t)kNSlot * 4 * K * c->NP));
-  HIPCHK(hipMemset(c->d_flag, c->r, K));
-  HIPCHK(hipMemset(c->d_allwet, 0, K));
+#define H2D(dst, src, n)                                                                       \
+  do {                                                                                         \
+    hipError_t e_ = hipMemcpy(dst, src, (n) * sizeof(*(src)), hipMemcpyHostToDevice);          \
+    if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e_)); \
+  } while (0)
+#define ZERO(dst, bytes)                                                                       \
+  do {                                                                                         \
+    hipError_t e_ = hipMemset(dst, 0, bytes);                                                  \
+    if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e_)); \
+  } while (0)
+  H2D(c->d_fA, fA.data(), c->F);
+  H2D(c->d_fB, fB.data(), c->F);
+  H2D(c->d_meta, meta.data(), c->F);
+  H2D(c->d_cmem, c->cmem.data(), K);
+  H2D(c->d_cdx, c->cdx.data(), K);
+  H2D(c->d_cw1, cw1.data(), K);
+  H2D(c->d_mtide, mtide.data(), 4 * (size_t)M);
+  H2D(c->d_mcfl, mcfl.data(), M);
+  H2D(c->d_fch, fch.data(), fch.size());
+  H2D(c->d_fch_m0, fch_m0.data(), M + 1);
+  H2D(c->d_cch, cch.data(), cch.size());
+  H2D(c->d_cch_m0, cch_m0.data(), M + 1);
+  ZERO(c->d_err, sizeof(int));
+  ZERO(c->d_db, sizeof(double) * K);
+  ZERO(c->d_nman, sizeof(double) * K);
+  ZERO(c->d_mt, sizeof(double) * M);
+  ZERO(c->d_mdt, sizeof(double) * M);
+  ZERO(c->d_mt_apply, sizeof(double) * M);
+  ZERO(c->d_mdiag, sizeof(double) * kMDiag * M);
+  ZERO(c->d_cdiag, sizeof(double) * (size_t)K * D_NSLOT);
+  ZERO(c->d_need, K);
+  ZERO(c->d_res, sizeof(double) * (size_t)kNSlot * 4 * K * c->NP);
+  ZERO(c->d_allwet, K);
   for (int q = 0; q < 4; ++q) {
-    HIPCHK(hipMemset(c->d_sn[q], 0, sizeof(double) * K * c->NP));
-    HIPCHK(hipMemset(c->d_ss[q], 0, sizeof(double) * K * c->NP));
+    ZERO(c->d_sn[q], sizeof(double) * K * c->NP);
+    ZERO(c->d_ss[q], sizeof(double) * K * c->NP);
   }
-  HIPCHK(hipMemset(c->d_hn, 0, sizeof(double) * K * c->NP));
-  HIPCHK(hipMemset(c->d_cn, 0, sizeof(double) * K * c->NP));
-  HIPCHK(hipDeviceSynchronize());
+  ZERO(c->d_hn, sizeof(double) * K * c->NP);
+  ZERO(c->d_cn, sizeof(double) * K * c->NP);
+  {
+    hipError_t e = hipMemset(c->d_flag, c->r, K);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+  }
+#undef H2D
+#undef ZERO
   *out = c;
   return SW_OK;
+}
+
+sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, void* stream) {
+  return sw_create_batch(out, 1, m, p, stream);
 }
 
 void sw_destroy(sw_ctx* c) {
@@ -886,13 +981,23 @@ sw_status sw_node_coords(const sw_ctx* c, double* xy) {
   for (const auto& L : c->lv) {
     for (int cl = 0; cl < L.ncell; ++cl) {
       const int k = L.cell0 + cl;
+      const double dx = c->cdx[k], x0 = c->mx0[c->cmem[k]], y0 = c->my0[c->cmem[k]];
       double* o = xy + 2 * (L.off + (size_t)cl * L.S * L.S);
       for (int b = 0; b < L.S; ++b)
         for (int a = 0; a < L.S; ++a) {
-          o[2 * (b * L.S + a) + 0] = c->x0 + (c->ci[k] + L.xh[a]) * L.dx;
-          o[2 * (b * L.S + a) + 1] = c->y0 + (c->cj[k] + L.xh[b]) * L.dx;
+          o[2 * (b * L.S + a) + 0] = x0 + (c->ci[k] + L.xh[a]) * dx;
+          o[2 * (b * L.S + a) + 1] = y0 + (c->cj[k] + L.xh[b]) * dx;
         }
     }
+  }
+  return SW_OK;
+}
+
+sw_status sw_cell_map(const sw_ctx* c, int32_t* member, int32_t* local) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  for (int k = 0; k < c->K; ++k) {
+    if (member) member[k] = c->cmem[k];
+    if (local) local[k] = c->cloc[k];
   }
   return SW_OK;
 }
@@ -902,12 +1007,12 @@ sw_status sw_dof_coords(const sw_ctx* c, double* xy) {
   std::vector<double> xi, wb;
   gll(c->N1, xi, wb);
   for (int k = 0; k < c->K; ++k) {
-    const double dx = c->lv[c->lev[k]].dx;
+    const double dx = c->cdx[k], x0 = c->mx0[c->cmem[k]], y0 = c->my0[c->cmem[k]];
     for (int jy = 0; jy < c->N1; ++jy)
       for (int jx = 0; jx < c->N1; ++jx) {
         const size_t q = (size_t)k * c->NP + jy * c->N1 + jx;
-        xy[2 * q + 0] = c->x0 + (c->ci[k] + xi[jx]) * dx;
-        xy[2 * q + 1] = c->y0 + (c->cj[k] + xi[jy]) * dx;
+        xy[2 * q + 0] = x0 + (c->ci[k] + xi[jx]) * dx;
+        xy[2 * q + 1] = y0 + (c->cj[k] + xi[jy]) * dx;
       }
   }
   return SW_OK;
@@ -997,7 +1102,7 @@ sw_status sw_init_lake_at_rest(sw_ctx* c, const double* eta) {
 
 sw_status sw_set_time(sw_ctx* c, double t) {
   if (!c) return fail(SW_EINVAL, "NULL context");
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, c->d_scal, 1, t);
+  hipLaunchKernelGGL(k_fill_n, dim3((c->M + 255) / 256), dim3(256), 0, c->s, c->d_mt, c->M, t);
   HIPCHK(hipGetLastError());
   return SW_OK;
 }
@@ -1010,8 +1115,9 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
   sw_status st = need_bathy(c);
   if (st != SW_OK) return st;
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_apply_operator cannot run inside an open step");
-  // the elevation boundary reads the time from scal[1]: evaluate at t with dt = 0
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, c->d_scal, 3, t);
+  // the elevation boundary is evaluated at t (stage offset 0)
+  hipLaunchKernelGGL(k_fill_n, dim3((c->M + 255) / 256), dim3(256), 0, c->s, c->d_mt_apply, c->M, t);
+  HIPCHK(hipGetLastError());
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
     a.in[0] = eta;
@@ -1022,8 +1128,7 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
     HIPCHK(launch_stage(c->r, L.P, M_APPLY, a, L.nblk, c->s));
   }
   const double* st4[4] = {eta, qx, qy, c->p.tracer ? tr : eta};
-  // the face kernel reads t from scal[1] = d_scal[3] (cstage = 0)
-  if ((st = faces(c, st4, 0.0, kApplySlot, c->d_scal + 2)) != SW_OK) return st;
+  if ((st = faces(c, st4, 0.0, kApplySlot, c->d_mt_apply)) != SW_OK) return st;
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
     a.slot = kApplySlot;
@@ -1034,11 +1139,10 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
     HIPCHK(launch_stage(c->r, L.P, M_FOLD, a, L.nblk, c->s));
   }
   if (dtb) {
-    if (c->fblk_total > 0) {
-      if ((st = reduce_dt(c, 1.0, dtb)) != SW_OK) return st;
-    } else {
-      hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, dtb, 0, 1e300);
-    }
+    // bare positivity bound, minimum over the members
+    if ((st = reduce_dt(c, nullptr, c->d_mtmp)) != SW_OK) return st;
+    hipLaunchKernelGGL(k_min_all, dim3(1), dim3(256), 0, c->s, c->d_mtmp, c->M, dtb);
+    HIPCHK(hipGetLastError());
   }
   c->start_ready = false;   // the apply slot does not disturb the step's data, but stay safe
   return SW_OK;
@@ -1050,7 +1154,10 @@ sw_status sw_step_begin(sw_ctx* c, double dt) {
   if (st != SW_OK) return st;
   if (c->stage_done != 0) return fail(SW_EINVAL, "a step is already open (call sw_rk_stage / sw_step_end)");
   c->fixed_dt = dt > 0.0;
-  if (c->fixed_dt) hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->s, c->d_scal, 0, dt);
+  if (c->fixed_dt) {
+    hipLaunchKernelGGL(k_fill_n, dim3((c->M + 255) / 256), dim3(256), 0, c->s, c->d_mdt, c->M, dt);
+    HIPCHK(hipGetLastError());
+  }
   // degree adaptation, H(zeta^n) and stage-1 volume terms (already in place after
   // a previous step's final kernel)
   if (!c->start_ready)
@@ -1058,7 +1165,7 @@ sw_status sw_step_begin(sw_ctx* c, double dt) {
   const double* stn[4] = {c->d_sn[0], c->d_sn[1], c->d_sn[2], c->d_sn[3]};
   if ((st = faces(c, stn, c->c[0], 0)) != SW_OK) return st;
   if (!c->fixed_dt)
-    if ((st = reduce_dt(c, c->p.cfl, c->d_scal)) != SW_OK) return st;
+    if ((st = reduce_dt(c, c->d_mcfl, c->d_mdt)) != SW_OK) return st;
   c->start_ready = false;
   c->stage_done = 1;
   return SW_OK;
@@ -1084,10 +1191,12 @@ sw_status sw_step_end(sw_ctx* c) {
   // final combination; the same pass prepares the next step's start (slot 0)
   sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2);
   if (st != SW_OK) return st;
-  const int nb = (c->K + 255) / 256;
-  hipLaunchKernelGGL(k_diag_part, dim3(nb), dim3(256), 0, c->s, c->d_cdiag, c->d_flag, c->K, c->d_red);
+  // per-member diagnostics (two-level segmented reduction); advances each member's time
+  hipLaunchKernelGGL(k_diag_part_seg, dim3(c->ncch), dim3(256), 0, c->s, c->d_cdiag, c->d_flag, c->d_cch,
+                     c->d_part);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, c->s, c->d_red, nb, c->d_diag, c->d_scal);
+  hipLaunchKernelGGL(k_diag_seg, dim3(c->M), dim3(256), 0, c->s, c->d_part, c->d_cch_m0, c->d_mdiag, c->d_mt,
+                     c->d_mdt);
   HIPCHK(hipGetLastError());
   c->stage_done = 0;
   c->start_ready = true;
@@ -1157,22 +1266,83 @@ sw_status sw_kernel_time_reset(sw_ctx* c) {
   return SW_OK;
 }
 
+}  // extern "C"
+
+// ---- hooks for the ensemble driver (sw_ens.hip) ----------------------------
+namespace swk {
+bool ctx_graph_ready(const sw_ctx* c) { return c->start_ready && c->stage_done == 0; }
+int64_t ctx_steps(const sw_ctx* c) { return c->nstep; }
+void ctx_set_steps(sw_ctx* c, int64_t n) { c->nstep = n; }
+bool ctx_set_prof(sw_ctx* c, bool on) {
+  const bool o = c->prof;
+  c->prof = on;
+  return o;
+}
+hipStream_t ctx_swap_stream(sw_ctx* c, hipStream_t s) {
+  hipStream_t o = c->s;
+  c->s = s;
+  return o;
+}
+hipStream_t ctx_stream(const sw_ctx* c) { return c->s; }
+int ctx_cells(const sw_ctx* c) { return c->K; }
+int api_fail(int status, const char* msg) { return (int)fail((sw_status)status, msg); }
+}  // namespace swk
+
+extern "C" {
+
+namespace {
+void fill_diag(const double* d, int64_t nstep, sw_diag* out) {
+  out->min_target_mass = d[D_MINT];
+  out->n_pos_viol = (int64_t)d[D_VIOL];
+  out->max_newton_it = (int32_t)d[D_NEWT];
+  out->n_fallback = (int64_t)d[D_FALLB];
+  out->total_mass = d[D_MASS];
+  out->n_r0_cells = (int64_t)d[D_NR0];
+  out->nonfinite = d[D_NONF] != 0.0;
+  out->dt = d[7];
+  out->t = d[8];
+  out->step = nstep;
+}
+}  // namespace
+
 sw_status sw_diagnostics(const sw_ctx* c, sw_diag* out) {
   if (!c || !out) return fail(SW_EINVAL, "NULL argument");
   HIPCHK(hipStreamSynchronize(c->s));
-  double d[16], s[8];
-  HIPCHK(hipMemcpy(d, c->d_diag, sizeof(d), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(s, c->d_scal, sizeof(s), hipMemcpyDeviceToHost));
-  out->min_target_mass = d[0];
-  out->n_pos_viol = (int64_t)d[1];
-  out->max_newton_it = (int32_t)d[2];
-  out->n_fallback = (int64_t)d[3];
-  out->total_mass = d[4];
-  out->n_r0_cells = (int64_t)d[5];
-  out->nonfinite = d[6] != 0.0;
-  out->dt = s[0];
-  out->t = s[1];
-  out->step = c->nstep;
+  std::vector<double> d((size_t)kMDiag * c->M);
+  HIPCHK(hipMemcpy(d.data(), c->d_mdiag, d.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // member 0 gives dt and t; the rest is combined over the members
+  double tot[kMDiag];
+  for (int q = 0; q < kMDiag; ++q) tot[q] = d[q];
+  for (int m = 1; m < c->M; ++m) {
+    const double* e = d.data() + (size_t)m * kMDiag;
+    tot[D_MINT] = std::min(tot[D_MINT], e[D_MINT]);
+    tot[D_VIOL] += e[D_VIOL];
+    tot[D_NEWT] = std::max(tot[D_NEWT], e[D_NEWT]);
+    tot[D_FALLB] += e[D_FALLB];
+    tot[D_MASS] += e[D_MASS];
+    tot[D_NR0] += e[D_NR0];
+    tot[D_NONF] = std::max(tot[D_NONF], e[D_NONF]);
+  }
+  // t and dt also before the first step (time set by sw_set_time)
+  double t0 = 0.0, dt0 = 0.0;
+  HIPCHK(hipMemcpy(&t0, c->d_mt, sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&dt0, c->d_mdt, sizeof(double), hipMemcpyDeviceToHost));
+  tot[7] = dt0;
+  tot[8] = t0;
+  fill_diag(tot, c->nstep, out);
+  if (out->nonfinite) return fail(SW_ENONFINITE, "non-finite value in the state");
+  return SW_OK;
+}
+
+sw_status sw_member_diagnostics(const sw_ctx* c, int32_t m, sw_diag* out) {
+  if (!c || !out) return fail(SW_EINVAL, "NULL argument");
+  if (m < 0 || m >= c->M) return fail(SW_EINVAL, "member index out of range");
+  HIPCHK(hipStreamSynchronize(c->s));
+  double d[kMDiag];
+  HIPCHK(hipMemcpy(d, c->d_mdiag + (size_t)m * kMDiag, sizeof(d), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&d[8], c->d_mt + m, sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&d[7], c->d_mdt + m, sizeof(double), hipMemcpyDeviceToHost));
+  fill_diag(d, c->nstep, out);
   if (out->nonfinite) return fail(SW_ENONFINITE, "non-finite value in the state");
   return SW_OK;
 }

@@ -57,8 +57,14 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
   const double g = A.g, eps = A.eps;
   const double dxA = A.cdx[cA];
   const double* tB0 = A.fl + (size_t)(sub < 0 ? 0 : 1 + sub) * S * N1;
-  const double tt = A.scal[1] + A.cstage * A.scal[0];
-  const double zeta_b = A.tide_amp * sin(6.283185307179586 * tt / A.tide_period + A.tide_phase);
+  double zeta_b = 0.0, c_in = 0.0;
+  if (bnd && bc == 1) {
+    const int m = A.cmem[cA];
+    const double* td = A.mtide + (size_t)m * 4;
+    const double tt = A.cstage != 0.0 ? A.mt[m] + A.cstage * A.mdt[m] : A.mt[m];
+    zeta_b = td[0] * sin(6.283185307179586 * tt / td[1] + td[2]);
+    c_in = td[3];
+  }
 
   double pA[NQ][N1], pB[NQ][N1];
 #pragma unroll
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
         vB[0] = zeta_b;
         vB[1] = vA[1];
         vB[2] = vA[2];
-        vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? A.tide_cin : vA[3];
+        vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? c_in : vA[3];
       } else {                  // open: copy
 #pragma unroll
         for (int q = 0; q < 4; ++q) vB[q] = vA[q];
@@ -163,8 +169,7 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
     bnd_dt = A.cw1[cA] * A.cdx[cA] * A.cdx[cA] / (lmax * dxA);
     if (!bnd) bnd_dt = fmin(bnd_dt, A.cw1[cB] * A.cdx[cB] * A.cdx[cB] / (lmax * dxA));
   }
-  bnd_dt = gmin<kWave>(bnd_dt);
-  if (tid == 0) A.bpart[A.bpart0 + blockIdx.x] = bnd_dt;
+  if (fv && lane == 0) A.fdt[f] = bnd_dt;
 }
 
 template <int R>

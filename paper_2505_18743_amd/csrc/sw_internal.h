@@ -29,11 +29,9 @@ struct LevelTabs {
   const double* mqinv;  // [NP][NP]     inverse exact mass matrix, unit square
   const double* meanw;  // [NP]         int psi_j over the unit square
   const double* fl;     // [3][S][N1]   l_k at face nodes: s, s/2, (1+s)/2
-  const double* dp;     // [S][N1]      l_k'(xhat_a) / dx
   const double* wl;     // [S][N1]      w_a l_k(xhat_a)
-  const double* wdp;    // [S][N1]      w_a l_k'(xhat_a) / dx
+  const double* wd;     // [S][N1]      w_a l_k'(xhat_a)
   int S;
-  double dx;
 };
 
 // diagnostics partial slots per stage-kernel block
@@ -46,6 +44,9 @@ struct StageArgs {
   const double* bvec;    // [K][NP] all-wet B_i = sum W psi_i zb
   const double* zmax;    // [K]     max depth sample
   const double* nman;    // [K]
+  const double* cdx;     // [K]     cell size
+  const int* cmem;       // [K]     member of the cell
+  const double* mdt;     // [M]     time step of each member
   double* sn[4];         // persistent state (zeta, qx, qy, c) [K][NP]
   double* ss[4];         // stage state
   const double* in[4];   // M_APPLY / M_TRACER inputs
@@ -59,7 +60,6 @@ struct StageArgs {
   double* cdiag;         // [K][D_NSLOT] per-cell diagnostics of the current step
   int diag_init;         // 1: first solve of the step initialises cdiag
   int8_t* allwet;        // [K] zeta^n wet at every sample node
-  const double* scal;    // device scalars: [0] dt, [1] t
   int* err;
   int slot;              // residual slot written (volume terms) or copied (M_FOLD)
   int nterm;             // number of stored residuals combined
@@ -79,22 +79,36 @@ struct FaceArgs {
   int slot;              // slot receiving the face terms
   const double* cdx;     // [K]
   const double* cw1;     // [K]
+  const int* cmem;       // [K] member of each cell
   const double* fl;      // [3][S][N1]
   const double* w;       // [S]
-  const double* scal;    // [0] dt, [1] t
+  const double* mt;      // [M] time of each member at the start of the step
+  const double* mdt;     // [M] time step of each member (unused when cstage = 0)
+  const double* mtide;   // [M][4] tide amplitude, period, phase, inflow tracer
   double cstage;         // c_l of the stage
-  double* bpart;         // per-block dt bounds
-  int bpart0;
+  double* fdt;           // [F] positivity bound of each face
   int* err;
   double g, eps;
   int tracer;
-  double tide_amp, tide_period, tide_phase, tide_cin;
 };
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s);
+
+// context hooks used by the ensemble driver
+}  // namespace swk
+struct sw_ctx;
+namespace swk {
+bool ctx_graph_ready(const sw_ctx* c);   // a step may be captured/replayed now
+int64_t ctx_steps(const sw_ctx* c);
+void ctx_set_steps(sw_ctx* c, int64_t n);
+bool ctx_set_prof(sw_ctx* c, bool on);   // returns the previous setting
+hipStream_t ctx_swap_stream(sw_ctx* c, hipStream_t s);   // returns the previous stream
+hipStream_t ctx_stream(const sw_ctx* c);
+int ctx_cells(const sw_ctx* c);
+int api_fail(int status, const char* msg);   // records msg for sw_last_error, returns status
 
 inline int lanes_for(int S) {
   int P = 4;

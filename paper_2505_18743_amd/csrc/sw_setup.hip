@@ -59,8 +59,8 @@ __global__ void k_facez(const int* fA, const int* fB, const int* meta, int face0
 }
 
 // Per cell: max depth sample and the all-wet B_i = sum_q W_q psi_i(x_q) zb_q.
-__global__ void k_cellinit(LevelTabs t, int cell0, int ncell, size_t off, int N1, const double* zb, double* bvec,
-                           double* zmax) {
+__global__ void k_cellinit(LevelTabs t, int cell0, int ncell, size_t off, int N1, const double* zb,
+                           const double* cdx, double* bvec, double* zmax) {
   const int NP = N1 * N1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ncell * NP) return;
@@ -78,7 +78,8 @@ __global__ void k_cellinit(LevelTabs t, int cell0, int ncell, size_t off, int N1
     }
     s += t.w[a] * t.l[a * N1 + ix] * sa;
   }
-  bvec[(size_t)(cell0 + cl) * NP + i] = s * t.dx * t.dx;
+  const double dx = cdx[cell0 + cl];
+  bvec[(size_t)(cell0 + cl) * NP + i] = s * dx * dx;
   if (i == 0) zmax[cell0 + cl] = mx;
 }
 
@@ -112,10 +113,6 @@ __global__ void k_lake(LevelTabs t, int cell0, int ncell, size_t off, int N1, co
   }
 }
 
-__global__ void k_set(double* p, int i, double v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[i] = v;
-}
-
 __global__ void k_fill(double* p, size_t n, double v) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;
@@ -131,46 +128,93 @@ __global__ void k_copy(const double* a, double* b, size_t n) {
   if (t < n) b[t] = a[t];
 }
 
-// Block-wise minimum: out[b] = min(in[b*1024 .. b*1024+1023]).
-__global__ void k_minred(const double* in, int n, double* out) {
-  __shared__ double sm[256];
-  const int base = blockIdx.x * 1024 + threadIdx.x;
-  double m = 1e300;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = base + u * 256;
-    if (i < n) m = fmin(m, in[i]);
-  }
+__global__ void k_fill_n(double* p, int n, double v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// Minimum over a block of 256 threads (every thread gets the result).
+__device__ double block_min(double m, double* sm) {
   sm[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+  const double r = sm[0];
+  __syncthreads();
+  return r;
 }
 
-// dt = cfl * min(in[0..n)) (or the fixed dt when fixed > 0); one block of 256.
-__global__ void k_dt(const double* in, int n, double cfl, double fixed, double* dst) {
+// Chunk minimum: chunk b covers in[ch[2b] .. ch[2b] + ch[2b+1]) (at most 1024 items).
+__global__ void k_minred_seg(const double* in, const int* ch, double* out) {
   __shared__ double sm[256];
+  const int b0 = ch[2 * blockIdx.x], n = ch[2 * blockIdx.x + 1];
   double m = 1e300;
-  for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, in[i]);
-  sm[threadIdx.x] = m;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, in[b0 + i]);
+  m = block_min(m, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
+
+// Member minimum over its chunks [m0[m], m0[m+1]), times the member's CFL number
+// (or 1 when cfl is NULL); one block per member.
+__global__ void k_dt_seg(const double* part, const int* m0, const double* cfl, double* dst) {
+  __shared__ double sm[256];
+  const int m = blockIdx.x;
+  double v = 1e300;
+  for (int i = m0[m] + threadIdx.x; i < m0[m + 1]; i += 256) v = fmin(v, part[i]);
+  v = block_min(v, sm);
+  if (threadIdx.x == 0) dst[m] = (cfl ? cfl[m] : 1.0) * v;
+}
+
+// *dst = min(in[0..n)); one block.
+__global__ void k_min_all(const double* in, int n, double* dst) {
+  __shared__ double sm[256];
+  double v = 1e300;
+  for (int i = threadIdx.x; i < n; i += 256) v = fmin(v, in[i]);
+  v = block_min(v, sm);
+  if (threadIdx.x == 0) *dst = v;
+}
+
+__device__ void diag_combine(double* a, const double* b) {
+  a[D_MINT] = fmin(a[D_MINT], b[D_MINT]);
+  a[D_VIOL] += b[D_VIOL];
+  a[D_NEWT] = fmax(a[D_NEWT], b[D_NEWT]);
+  a[D_FALLB] += b[D_FALLB];
+  a[D_MASS] += b[D_MASS];
+  a[D_NR0] += b[D_NR0];
+  a[D_NONF] = fmax(a[D_NONF], b[D_NONF]);
+}
+
+// Tree reduction of per-thread diagnostics over a block of 256 (fixed order);
+// the result is left in s[.][0].
+__device__ void block_diag(const double* v, double (*s)[256]) {
+  const int t = threadIdx.x;
+  for (int q = 0; q < D_NSLOT; ++q) s[q][t] = v[q];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st) {
+      double a[D_NSLOT], b[D_NSLOT];
+      for (int q = 0; q < D_NSLOT; ++q) {
+        a[q] = s[q][t];
+        b[q] = s[q][t + st];
+      }
+      diag_combine(a, b);
+      for (int q = 0; q < D_NSLOT; ++q) s[q][t] = a[q];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *dst = fixed > 0.0 ? fixed : cfl * sm[0];
 }
 
-// Per-cell diagnostics -> per-block partials (256 cells per block).
-__global__ void k_diag_part(const double* cdiag, const int8_t* flag, int K, double* part) {
+// Per-cell diagnostics of one cell chunk (at most 256 cells of one member) ->
+// chunk partials.
+__global__ void k_diag_part_seg(const double* cdiag, const int8_t* flag, const int* ch, double* part) {
   __shared__ double s[D_NSLOT][256];
   const int t = threadIdx.x;
-  const int c = blockIdx.x * 256 + t;
+  const int c0 = ch[2 * blockIdx.x], n = ch[2 * blockIdx.x + 1];
   double v[D_NSLOT] = {1e300, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c < K) {
+  if (t < n) {
+    const int c = c0 + t;
     const double* d = cdiag + (size_t)c * D_NSLOT;
     v[D_MINT] = d[D_MINT];
     v[D_VIOL] = d[D_VIOL];
@@ -180,58 +224,25 @@ __global__ void k_diag_part(const double* cdiag, const int8_t* flag, int K, doub
     v[D_NR0] = flag[c] == 0 ? 1.0 : 0.0;
     v[D_NONF] = d[D_NONF];
   }
-  for (int q = 0; q < D_NSLOT; ++q) s[q][t] = v[q];
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (t < st) {
-      s[D_MINT][t] = fmin(s[D_MINT][t], s[D_MINT][t + st]);
-      s[D_VIOL][t] += s[D_VIOL][t + st];
-      s[D_NEWT][t] = fmax(s[D_NEWT][t], s[D_NEWT][t + st]);
-      s[D_FALLB][t] += s[D_FALLB][t + st];
-      s[D_MASS][t] += s[D_MASS][t + st];
-      s[D_NR0][t] += s[D_NR0][t + st];
-      s[D_NONF][t] = fmax(s[D_NONF][t], s[D_NONF][t + st]);
-    }
-    __syncthreads();
-  }
+  block_diag(v, s);
   if (t == 0)
     for (int q = 0; q < D_NSLOT; ++q) part[(size_t)blockIdx.x * D_NSLOT + q] = s[q][0];
 }
 
-// End of step: reduce the block partials in a fixed order and advance t.
-__global__ void k_diag(const double* part, int n, double* diag, double* scal) {
+// End of step, one block per member: reduce the member's chunk partials in a
+// fixed order into mdiag[m][0..D_NSLOT), record dt and advance the member's time.
+__global__ void k_diag_seg(const double* part, const int* m0, double* mdiag, double* mt, const double* mdt) {
   __shared__ double s[D_NSLOT][256];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, m = blockIdx.x;
   double v[D_NSLOT] = {1e300, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = t; i < n; i += 256) {
-    const double* d = part + (size_t)i * D_NSLOT;
-    v[D_MINT] = fmin(v[D_MINT], d[D_MINT]);
-    v[D_VIOL] += d[D_VIOL];
-    v[D_NEWT] = fmax(v[D_NEWT], d[D_NEWT]);
-    v[D_FALLB] += d[D_FALLB];
-    v[D_MASS] += d[D_MASS];
-    v[D_NR0] += d[D_NR0];
-    v[D_NONF] = fmax(v[D_NONF], d[D_NONF]);
-  }
-  for (int q = 0; q < D_NSLOT; ++q) s[q][t] = v[q];
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (t < st) {
-      s[D_MINT][t] = fmin(s[D_MINT][t], s[D_MINT][t + st]);
-      s[D_VIOL][t] += s[D_VIOL][t + st];
-      s[D_NEWT][t] = fmax(s[D_NEWT][t], s[D_NEWT][t + st]);
-      s[D_FALLB][t] += s[D_FALLB][t + st];
-      s[D_MASS][t] += s[D_MASS][t + st];
-      s[D_NR0][t] += s[D_NR0][t + st];
-      s[D_NONF][t] = fmax(s[D_NONF][t], s[D_NONF][t + st]);
-    }
-    __syncthreads();
-  }
+  for (int i = m0[m] + t; i < m0[m + 1]; i += 256) diag_combine(v, part + (size_t)i * D_NSLOT);
+  block_diag(v, s);
   if (t == 0) {
-    for (int q = 0; q < D_NSLOT; ++q) diag[q] = s[q][0];
-    diag[7] = scal[0];
-    scal[1] += scal[0];
-    diag[8] = scal[1];
+    double* d = mdiag + (size_t)m * 16;
+    for (int q = 0; q < D_NSLOT; ++q) d[q] = s[q][0];
+    d[7] = mdt[m];
+    mt[m] += mdt[m];
+    d[8] = mt[m];
   }
 }
 

@@ -48,6 +48,8 @@ class Raster:
         self.v = np.ascontiguousarray(values, dtype=np.float64)   # [ny, nx]
 
     def sample(self, x, y):
+        if type(x).__module__.startswith("torch"):
+            return self._sample_torch(x, y)
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
         ny, nx = self.v.shape
@@ -57,6 +59,19 @@ class Raster:
         j = np.minimum(fy.astype(np.int64), ny - 2)
         tx, ty = fx - i, fy - j
         v = self.v
+        return ((1 - ty) * ((1 - tx) * v[j, i] + tx * v[j, i + 1])
+                + ty * ((1 - tx) * v[j + 1, i] + tx * v[j + 1, i + 1]))
+
+    def _sample_torch(self, x, y):
+        """The same interpolation on torch tensors (any device)."""
+        import torch
+        v = torch.as_tensor(self.v, device=x.device)
+        ny, nx = self.v.shape
+        fx = ((x - self.x0) / self.h).clamp(0.0, nx - 1.0)
+        fy = ((y - self.y0) / self.h).clamp(0.0, ny - 1.0)
+        i = fx.to(torch.int64).clamp(max=nx - 2)
+        j = fy.to(torch.int64).clamp(max=ny - 2)
+        tx, ty = fx - i, fy - j
         return ((1 - ty) * ((1 - tx) * v[j, i] + tx * v[j, i + 1])
                 + ty * ((1 - tx) * v[j + 1, i] + tx * v[j + 1, i + 1]))
 
