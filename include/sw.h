@@ -182,6 +182,39 @@ sw_status sw_step_end(sw_ctx *c);
 sw_status sw_step(sw_ctx *c, double dt);
 sw_status sw_run(sw_ctx *c, int32_t n_steps, double dt);
 
+/* ---- adjoint (vector-Jacobian products; the paper has no adjoint) ----
+ * R(u) = (F, Gx, Gy) are the weak residuals of sw_apply_operator (without a
+ * tracer); n_K the Manning coefficients and db_K the bed-elevation offsets of
+ * sw_set_manning / sw_set_bed_offset.  Kinks take the forward's branch:
+ * max(x, 0) has derivative 1 iff x > 0, ties of max/min (Rusanov speed,
+ * z*_b = min(zb-, zb+), zeta* = max(zeta, -z*_b)) go to the A (interior) side,
+ * d|x|/dx = sign(x) with sign(0) = 0; dry nodes give zero depth derivatives.
+ *
+ * sw_vjp_operator: for the state (eta, qx, qy) (device [n_dofs] each) and
+ * adjoint residuals Fb, Gxb, Gyb (device [n_dofs]), writes
+ * eta_b, qx_b, qy_b = (dR/du)^T (Fb, Gxb, Gyb) and n_bar, db_bar
+ * (device [n_cells]) = (dR/dn)^T ..., (dR/ddb)^T ...; t is the time of the
+ * elevation boundary.  Overwrites its outputs. */
+sw_status sw_vjp_operator(sw_ctx *c, const double *eta, const double *qx, const double *qy, double t,
+                          const double *Fb, const double *Gxb, const double *Gyb, double *eta_b, double *qx_b,
+                          double *qy_b, double *n_bar, double *db_bar);
+/* sw_step_record: one step with the fixed dt > 0 (as sw_step) that also
+ * stores its stage states u^(1) = u^n, u^(2), ..., u^(s) into stages (device
+ * [s][3][n_dofs]: zeta, qx, qy per stage).
+ * sw_vjp_step: adjoint of that step in the all-wet regime (every rule node wet
+ * in every stage, every cell of degree r, no tracer), where the step is the
+ * explicit map u^(l) = u^n + dt M^-1 sum_m a_lm R(u^(m)) of Sec. 3.1 with M the
+ * all-wet rule mass matrix for zeta (eq:depth_rhs is affine there, so the
+ * Newton solve of eq:newton is exact after one iteration) and the exact mass
+ * matrix for q.  state_bar (device [3][n_dofs]) holds the adjoint of u^(n+1)
+ * on entry and that of u^n on return; n_bar and db_bar (device [n_cells]) are
+ * accumulated.  t is the step's start time.  A stage state outside the regime
+ * makes the next sw_sync report SW_EDEVICE (code 4).  Uses the context's
+ * residual storage: the next step recomputes its start-of-step terms. */
+sw_status sw_step_record(sw_ctx *c, double dt, double *stages_dev);
+sw_status sw_vjp_step(sw_ctx *c, const double *stages_dev, double t, double dt, double *state_bar,
+                      double *n_bar, double *db_bar);
+
 /* Diagnostics of the last step (host output).  Synchronises.  In a batched
  * context dt and t are member 0's; masses and counts are summed, extrema
  * taken over the members.  sw_member_diagnostics gives one member's. */

@@ -24,7 +24,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync"]
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -78,6 +78,9 @@ def load():
     L.sw_ens_member.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.sw_ens_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
     L.sw_ens_sync.argtypes = [vp]
+    L.sw_vjp_operator.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.sw_step_record.argtypes = [vp, ctypes.c_double, vp]
+    L.sw_vjp_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
     L.sw_last_error.restype = ctypes.c_char_p
@@ -348,6 +351,34 @@ class Solver:
 
     def sync(self):
         _check(load().sw_sync(self.h), "sw_sync")
+
+    # ---- adjoint ----
+    def vjp_operator(self, eta, qx, qy, Fb, Gxb, Gyb, t=0.0):
+        """(eta_b, qx_b, qy_b, n_bar, db_bar): transpose of the residual Jacobian."""
+        ins = [self._dev(a, self.n_dofs) for a in (eta, qx, qy, Fb, Gxb, Gyb)]
+        outs = [self.zeros() for _ in range(3)]
+        pb = [torch.zeros(self.n_cells, dtype=torch.float64, device=self.dev) for _ in range(2)]
+        _check(load().sw_vjp_operator(self.h, *[_ptr(x) for x in ins[:3]], float(t), *[_ptr(x) for x in ins[3:]],
+                                      *[_ptr(x) for x in outs], *[_ptr(x) for x in pb]), "sw_vjp_operator")
+        return outs[0], outs[1], outs[2], pb[0], pb[1]
+
+    def n_stages(self):
+        return {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[self.params.get("rk", "ssp3")]
+
+    def step_record(self, dt, stages):
+        """One fixed-dt step storing its stage states into `stages` [s, 3, n_dofs]."""
+        if stages.numel() != self.n_stages() * 3 * self.n_dofs or not stages.is_contiguous():
+            raise ValueError("stages must be a contiguous [s, 3, n_dofs] float64 tensor")
+        _check(load().sw_step_record(self.h, float(dt), _ptr(stages)), "sw_step_record")
+
+    def vjp_step(self, stages, t, dt, state_bar, n_bar, db_bar):
+        """Adjoint of one recorded step: state_bar [3, n_dofs] updated in place
+        (adjoint of u^(n+1) -> of u^n); n_bar, db_bar [n_cells] accumulated."""
+        for x, n in ((state_bar, 3 * self.n_dofs), (n_bar, self.n_cells), (db_bar, self.n_cells)):
+            if x.numel() != n or not x.is_contiguous() or x.dtype != torch.float64:
+                raise ValueError("adjoint arrays must be contiguous float64 of the right size")
+        _check(load().sw_vjp_step(self.h, _ptr(stages), float(t), float(dt), _ptr(state_bar), _ptr(n_bar),
+                                  _ptr(db_bar)), "sw_vjp_step")
 
     def profile(self, on=True):
         _check(load().sw_profile(self.h, int(bool(on))), "sw_profile")

@@ -44,6 +44,21 @@ __global__ void k_diag_seg(const double*, const int*, double*, double*, const do
 hipError_t launch_elem_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_vjp_vol_r1(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
+hipError_t launch_vjp_vol_r2(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
+hipError_t launch_vjp_vol_r3(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
+__global__ void k_gather_fdb(const double*, const int*, const int*, int, double*);
+__global__ void k_vjp_combine(double*, double*, double*, const double*, int, size_t);
+
+hipError_t launch_vjp_vol(int r, int P, int mode, const VjpArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return launch_vjp_vol_r1(P, mode, a, nblk, s);
+    case 2: return launch_vjp_vol_r2(P, mode, a, nblk, s);
+    case 3: return launch_vjp_vol_r3(P, mode, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
@@ -245,6 +260,10 @@ struct sw_ctx {
   int *d_fch = nullptr, *d_fch_m0 = nullptr, *d_cch = nullptr, *d_cch_m0 = nullptr;
   int nfch = 0, ncch = 0;
   int8_t *d_flag = nullptr, *d_allwet = nullptr, *d_need = nullptr;
+  // adjoint: per-face bed-offset parts [F][2] and, per cell, the list of its
+  // entries in that array (CSR, face order)
+  double* d_fdb = nullptr;
+  int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
   bool fixed_dt = false;
   bool bathy_set = false;
@@ -890,6 +909,9 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_need, K);
     ALLOC(c->d_flag, K);
     ALLOC(c->d_allwet, K);
+    ALLOC(c->d_fdb, (size_t)2 * c->F);
+    ALLOC(c->d_cfoff, (size_t)K + 1);
+    ALLOC(c->d_cfent, (size_t)2 * c->F);
 #undef ALLOC
   }
   for (auto& L : c->lv) {
@@ -930,6 +952,22 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   H2D(c->d_fch_m0, fch_m0.data(), M + 1);
   H2D(c->d_cch, cch.data(), cch.size());
   H2D(c->d_cch_m0, cch_m0.data(), M + 1);
+  {
+    // cell -> entries of the per-face adjoint array: A side 2f, B side 2f+1
+    std::vector<int> cnt((size_t)K + 1, 0), ent((size_t)2 * c->F);
+    for (int f = 0; f < c->F; ++f) {
+      ++cnt[fA[f] + 1];
+      if (!fh[f].bnd) ++cnt[fB[f] + 1];
+    }
+    for (int k = 0; k < K; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int f = 0; f < c->F; ++f) {
+      ent[pos[fA[f]]++] = 2 * f;
+      if (!fh[f].bnd) ent[pos[fB[f]]++] = 2 * f + 1;
+    }
+    H2D(c->d_cfoff, cnt.data(), (size_t)K + 1);
+    if (cnt[K] > 0) H2D(c->d_cfent, ent.data(), (size_t)cnt[K]);
+  }
   ZERO(c->d_err, sizeof(int));
   ZERO(c->d_db, sizeof(double) * K);
   ZERO(c->d_nman, sizeof(double) * K);
@@ -1210,6 +1248,169 @@ sw_status sw_step(sw_ctx* c, double dt) {
   for (int l = 2; l <= c->ns; ++l)
     if ((st = sw_rk_stage(c, l)) != SW_OK) return st;
   return sw_step_end(c);
+}
+
+sw_status sw_step_record(sw_ctx* c, double dt, double* stages) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!stages) return fail(SW_EINVAL, "stages must be non-NULL");
+  if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_step_record needs a fixed dt > 0");
+  const size_t KN = (size_t)c->K * c->NP;
+  const unsigned nb = (unsigned)((KN + 255) / 256);
+  auto save = [&](double* const* src, int l) -> sw_status {
+    for (int f = 0; f < 3; ++f) {
+      hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, c->s, src[f], stages + ((size_t)l * 3 + f) * KN, KN);
+      HIPCHK(hipGetLastError());
+    }
+    return SW_OK;
+  };
+  sw_status st = save(c->d_sn, 0);
+  if (st != SW_OK) return st;
+  if ((st = sw_step_begin(c, dt)) != SW_OK) return st;
+  for (int l = 2; l <= c->ns; ++l) {
+    if ((st = sw_rk_stage(c, l)) != SW_OK) return st;
+    if ((st = save(c->d_ss, l - 1)) != SW_OK) return st;
+  }
+  return sw_step_end(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+VjpArgs vjp_args(sw_ctx* c, const LevelH& L) {
+  VjpArgs a{};
+  a.t = L.tabs;
+  a.cell0 = L.cell0;
+  a.ncell = L.ncell;
+  a.K = c->K;
+  a.zb = c->d_zb + L.off;
+  a.nman = c->d_nman;
+  a.cdx = c->d_cdx;
+  a.err = c->d_err;
+  a.g = c->p.g;
+  a.eps = c->p.eps;
+  a.hlim = c->p.h_lim;
+  return a;
+}
+
+// face part of the residual VJP for every level and class, then the per-cell
+// gather of the bed-offset parts
+sw_status vjp_faces(sw_ctx* c, const double* const* u, const double* const* rb, double* const* ub, double tt,
+                    double* dbbar) {
+  for (auto& L : c->lv)
+    for (int k = 0; k < 6; ++k) {
+      if (L.cnface[k] == 0) continue;
+      VjpFaceArgs a{};
+      a.face0 = L.cface0[k];
+      a.nface = L.cnface[k];
+      a.K = c->K;
+      a.S = L.S;
+      a.fA = c->d_fA;
+      a.fB = c->d_fB;
+      a.meta = c->d_meta;
+      a.zf = c->d_zf + L.zfoff + (size_t)(L.cface0[k] - L.face0) * 2 * L.S;
+      for (int f = 0; f < 3; ++f) {
+        a.u[f] = u[f];
+        a.rb[f] = rb[f];
+        a.ub[f] = ub[f];
+      }
+      a.fdb = c->d_fdb;
+      a.cdx = c->d_cdx;
+      a.cmem = c->d_cmem;
+      a.fl = L.tabs.fl;
+      a.w = L.tabs.w;
+      a.mtide = c->d_mtide;
+      a.tt = tt;
+      a.err = c->d_err;
+      a.g = c->p.g;
+      a.eps = c->p.eps;
+      HIPCHK(launch_vjp_face(c->r, a, L.cfnblk[k], c->s));
+    }
+  hipLaunchKernelGGL(k_gather_fdb, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_fdb, c->d_cfoff, c->d_cfent,
+                     c->K, dbbar);
+  HIPCHK(hipGetLastError());
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_vjp_operator(sw_ctx* c, const double* eta, const double* qx, const double* qy, double t,
+                          const double* Fb, const double* Gxb, const double* Gyb, double* eta_b, double* qx_b,
+                          double* qy_b, double* n_bar, double* db_bar) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!eta || !qx || !qy || !Fb || !Gxb || !Gyb || !eta_b || !qx_b || !qy_b || !n_bar || !db_bar)
+    return fail(SW_EINVAL, "all arrays of sw_vjp_operator must be non-NULL");
+  sw_status st = need_bathy(c);
+  if (st != SW_OK) return st;
+  const unsigned nbk = (unsigned)((c->K + 255) / 256);
+  hipLaunchKernelGGL(k_fill, dim3(nbk), dim3(256), 0, c->s, n_bar, (size_t)c->K, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nbk), dim3(256), 0, c->s, db_bar, (size_t)c->K, 0.0);
+  HIPCHK(hipGetLastError());
+  const double* u[3] = {eta, qx, qy};
+  const double* rb[3] = {Fb, Gxb, Gyb};
+  double* ub[3] = {eta_b, qx_b, qy_b};
+  for (auto& L : c->lv) {
+    VjpArgs a = vjp_args(c, L);
+    for (int f = 0; f < 3; ++f) {
+      a.u[f] = u[f];
+      a.rin[f] = rb[f];
+      a.ub[f] = ub[f];
+    }
+    a.nbar = n_bar;
+    a.dbbar = db_bar;
+    HIPCHK(launch_vjp_vol(c->r, L.P, V_OP, a, L.nblk, c->s));
+  }
+  return vjp_faces(c, u, rb, ub, t, db_bar);
+}
+
+sw_status sw_vjp_step(sw_ctx* c, const double* stages, double t, double dt, double* state_bar, double* n_bar,
+                      double* db_bar) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!stages || !state_bar || !n_bar || !db_bar) return fail(SW_EINVAL, "arrays of sw_vjp_step must be non-NULL");
+  if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_vjp_step needs the step's fixed dt > 0");
+  if (c->p.tracer) return fail(SW_EINVAL, "the step adjoint covers runs without a tracer");
+  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_vjp_step cannot run inside an open step");
+  sw_status st = need_bathy(c);
+  if (st != SW_OK) return st;
+  const size_t KN = (size_t)c->K * c->NP;
+  const int ns = c->ns;
+  double* sb[3] = {state_bar, state_bar + KN, state_bar + 2 * KN};
+  auto slot = [&](int l, int f) { return c->d_res + ((size_t)l * 4 + f) * KN; };
+  for (int l = ns; l >= 1; --l) {
+    const double* u[3];
+    for (int f = 0; f < 3; ++f) u[f] = stages + ((size_t)(l - 1) * 3 + f) * KN;
+    double* ub[3] = {slot(l - 1, 0), slot(l - 1, 1), slot(l - 1, 2)};
+    const double* rb[3] = {c->d_ss[0], c->d_ss[1], c->d_ss[2]};
+    for (auto& L : c->lv) {
+      VjpArgs a = vjp_args(c, L);
+      for (int f = 0; f < 3; ++f) {
+        a.u[f] = u[f];
+        a.rbar[f] = c->d_ss[f];
+        a.ub[f] = ub[f];
+        a.yb[0][f] = sb[f];
+      }
+      a.yc[0] = c->b[l - 1];
+      int ny = 1;
+      for (int m = l + 1; m <= ns; ++m, ++ny) {
+        for (int f = 0; f < 3; ++f) a.yb[ny][f] = slot(m - 1, f);
+        a.yc[ny] = c->A[m - 1][l - 1];
+      }
+      a.ny = ny;
+      a.dt = dt;
+      a.nbar = n_bar;
+      a.dbbar = db_bar;
+      a.check = (l == 1 && c->p.adapt_degree) ? 2 : 1;
+      HIPCHK(launch_vjp_vol(c->r, L.P, V_STEP, a, L.nblk, c->s));
+    }
+    if ((st = vjp_faces(c, u, rb, ub, t + c->c[l - 1] * dt, db_bar)) != SW_OK) return st;
+  }
+  hipLaunchKernelGGL(k_vjp_combine, dim3((unsigned)((KN + 255) / 256)), dim3(256), 0, c->s, sb[0], sb[1], sb[2],
+                     (const double*)c->d_res, ns, KN);
+  HIPCHK(hipGetLastError());
+  c->start_ready = false;   // the residual slots were used as scratch
+  return SW_OK;
 }
 
 sw_status sw_run(sw_ctx* c, int32_t n, double dt) {

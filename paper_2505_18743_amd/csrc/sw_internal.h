@@ -92,6 +92,56 @@ struct FaceArgs {
   int tracer;
 };
 
+// ---- adjoint (vector-Jacobian products) ----------------------------------
+enum VjpMode : int {
+  V_OP = 0,     // adjoint residual coefficients given
+  V_STEP = 1,   // adjoint residual = dt M^-1 y, y combined from stage adjoints
+};
+
+struct VjpArgs {
+  LevelTabs t;
+  int cell0, ncell, K;
+  const double* zb;      // level block of depth samples [ncell][S(a)][S(b)]
+  const double* nman;    // [K]
+  const double* cdx;     // [K]
+  const double* u[3];    // state at which the residual is linearised [K][NP]
+  const double* rin[3];  // V_OP: adjoint residual coefficients
+  const double* yb[4][3];  // V_STEP: y = sum_{m < ny} yc[m] yb[m]
+  double yc[4];
+  int ny;
+  double dt;             // V_STEP: R_bar = dt M^-1 y
+  double* rbar[3];       // V_STEP: R_bar written for the face kernel
+  double* ub[3];         // volume part of the state adjoint (written)
+  double* nbar;          // [K] Manning adjoint (accumulated)
+  double* dbbar;         // [K] bed-offset adjoint (accumulated)
+  int* err;
+  double g, eps, hlim;
+  int check;             // 0: none, 1: every node wet, 2: also min depth >= hlim
+};
+
+struct VjpFaceArgs {
+  int face0, nface, K, S;
+  const int* fA;
+  const int* fB;
+  const int* meta;
+  const double* zf;      // group block [nface][2][S]
+  const double* u[3];    // state (traces)
+  const double* rb[3];   // adjoint residual coefficients
+  double* ub[3];         // state adjoint: face rows added
+  double* fdb;           // [F][2] bed-offset adjoint parts of each face (A side, B side)
+  const double* cdx;     // [K]
+  const int* cmem;       // [K]
+  const double* fl;      // [3][S][N1]
+  const double* w;       // [S]
+  const double* mtide;   // [M][4]
+  double tt;             // time of the stage (elevation boundary)
+  int* err;
+  double g, eps;
+};
+
+hipError_t launch_vjp_vol(int r, int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
+hipError_t launch_vjp_face(int r, const VjpFaceArgs& a, int nblk, hipStream_t s);
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
