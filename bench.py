@@ -173,6 +173,61 @@ def ensemble_bench(steps, warmup, device):
                 graph_speedup_vs_eager=res["eager"] / res["graph"])
 
 
+def adjoint_bench(device, reps=3):
+    """Gradient of the gauge misfit (adjoint_128: 128x128, r=2, 200 fixed-dt
+    SSP3 steps, checkpoints every 20) w.r.t. per-cell Manning and bed offsets:
+    forward and backward wall time and their ratio."""
+    import torch
+    from paper_2505_18743_amd import Solver
+    from paper_2505_18743_amd.adjoint import PointObservation, observed_run
+    from workloads import workload
+    wl = workload("adjoint_128")
+    s = Solver(wl["mesh"], wl["params"], device)
+    xy = s.node_coords()
+    s.set_bathymetry(wl["bed"](xy[:, 0], xy[:, 1]))
+    dof = s.dof_coords()
+    s.init_lake_at_rest(wl["eta0"](dof[:, 0], dof[:, 1]))
+    state0 = [x.clone() for x in s.get_state()[:3]]
+    K = s.n_cells
+    dt = 0.9 * float(s.apply_operator(*state0)[4].cpu()[0])
+    cells, phi = s.locate_points(wl["gauges"])
+    obs = PointObservation(cells, phi, s.np_, device)
+    nsteps, ck = int(wl["steps"]), int(wl["checkpoint_every"])
+    zeros = torch.zeros(K, dtype=torch.float64, device=device)
+    truth = observed_run(s, torch.as_tensor(wl["manning_truth"], device=device), zeros, state0, 0.0, dt, nsteps,
+                         obs).detach()
+    n0 = torch.as_tensor(wl["manning"], dtype=torch.float64, device=device)
+    tf, tb, tp = [], [], []
+    for rep in range(reps + 1):
+        nman = n0.clone().requires_grad_(True)
+        dbed = zeros.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = observed_run(s, nman, dbed, state0, 0.0, dt, nsteps, obs, checkpoint_every=ck)
+        loss = ((out - truth) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.set_state(*state0)
+        s.set_time(0.0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        s.run(nsteps, dt)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        if rep > 0:
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+            tp.append(t4 - t3)
+    s.sync()
+    f, b, p = min(tf), min(tb), min(tp)
+    return dict(workload="adjoint_128", cells=K, params=2 * K, steps=nsteps, checkpoint_every=ck,
+                forward_ms=f * 1e3, backward_ms=b * 1e3, plain_forward_ms=p * 1e3,
+                adjoint_over_forward=b / f, adjoint_over_plain_forward=b / p, loss=float(loss.detach()))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +237,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=300, help="ensemble_64 steps per mode (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint_128 gradient timing")
+    ap.add_argument("--only", choices=["ensemble", "adjoint"], default=None,
+                    help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -196,6 +254,12 @@ def main():
         print("bench.py needs a GPU (HIP device)", file=sys.stderr)
         sys.exit(1)
     dev = "cuda:0"
+    if args.only == "ensemble":
+        print(json.dumps(ensemble_bench(args.ens_steps, 3, dev)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(adjoint_bench(dev)), flush=True)
+        return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
     stages = {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[wl["params"]["rk"]]
@@ -267,6 +331,8 @@ def main():
     line["config"]["r0_cells"] = diag["n_r0_cells"]
     if args.ens_steps > 0:
         line["ensemble"] = ensemble_bench(args.ens_steps, 3, dev)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_bench(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     else:

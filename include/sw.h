@@ -133,6 +133,13 @@ sw_status sw_create_batch(sw_ctx **out, int32_t n_members, const sw_mesh_desc *m
 /* Host outputs [n_cells]: member of each cell and its index in that member's
  * description (either may be NULL). */
 sw_status sw_cell_map(const sw_ctx *c, int32_t *member_host, int32_t *local_host);
+/* Point evaluation of nodal fields (gauges): for n points xy_host [n][2] of a
+ * member, the containing cell (context numbering, cell_host [n]) and the basis
+ * values phi_host [n][(r+1)^2] (layout [jy][jx]), so that a field's value at
+ * point g is sum_j phi[g][j] field[cell[g]][j].  Host computation; SW_EINVAL
+ * for a point outside the member's mesh (cells are half-open [x, x+dx)). */
+sw_status sw_locate_points(const sw_ctx *c, int32_t member, int32_t n, const double *xy_host, int32_t *cell_host,
+                           double *phi_host);
 
 /* Sizes: cells, sample nodes (sum of S_L^2), nodal values per field. */
 sw_status sw_counts(const sw_ctx *c, int64_t *n_cells, int64_t *n_vol_nodes, int64_t *n_dofs);

@@ -24,7 +24,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step"]
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -80,6 +80,7 @@ def load():
     L.sw_ens_sync.argtypes = [vp]
     L.sw_vjp_operator.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sw_step_record.argtypes = [vp, ctypes.c_double, vp]
+    L.sw_locate_points.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.sw_vjp_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
@@ -256,6 +257,16 @@ class Solver:
     def member_part(self, t, m, kind):
         col = {"cells": 0, "nodes": 1, "dofs": 2}[kind]
         return t[torch.as_tensor(self.member_index(m)[col], device=self.dev)]
+
+    def locate_points(self, xy, member=0):
+        """(cell, phi): containing cell and basis values of each point."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        cell = np.zeros(len(xy), dtype=np.int32)
+        phi = np.zeros((len(xy), self.np_))
+        _check(load().sw_locate_points(self.h, int(member), len(xy), xy.ctypes.data_as(ctypes.c_void_p),
+                                       cell.ctypes.data_as(ctypes.c_void_p), phi.ctypes.data_as(ctypes.c_void_p)),
+               "sw_locate_points")
+        return cell, phi
 
     def member_diagnostics(self, m):
         d = SwDiag()
@@ -482,6 +493,16 @@ class Ensemble:
         b, i = self.where[m]
         s = self.batches[b]
         return [s.member_part(x, i, "dofs") for x in s.get_state()]
+
+    def locate_points(self, xy, member=0):
+        """(cell, phi): containing cell and basis values of each point."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        cell = np.zeros(len(xy), dtype=np.int32)
+        phi = np.zeros((len(xy), self.np_))
+        _check(load().sw_locate_points(self.h, int(member), len(xy), xy.ctypes.data_as(ctypes.c_void_p),
+                                       cell.ctypes.data_as(ctypes.c_void_p), phi.ctypes.data_as(ctypes.c_void_p)),
+               "sw_locate_points")
+        return cell, phi
 
     def member_diagnostics(self, m):
         b, i = self.where[m]

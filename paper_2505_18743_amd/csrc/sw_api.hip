@@ -1031,6 +1031,34 @@ sw_status sw_node_coords(const sw_ctx* c, double* xy) {
   return SW_OK;
 }
 
+sw_status sw_locate_points(const sw_ctx* c, int32_t member, int32_t n, const double* xy, int32_t* cell,
+                           double* phi) {
+  if (!c || (n > 0 && (!xy || !cell || !phi))) return fail(SW_EINVAL, "NULL argument");
+  if (member < 0 || member >= c->M) return fail(SW_EINVAL, "member index out of range");
+  std::vector<double> xi, wb;
+  gll(c->N1, xi, wb);
+  for (int g = 0; g < n; ++g) {
+    const double x = xy[2 * g], y = xy[2 * g + 1];
+    int found = -1;
+    double rx = 0.0, ry = 0.0;
+    for (int k = 0; k < c->K && found < 0; ++k) {
+      if (c->cmem[k] != member) continue;
+      const double dx = c->cdx[k];
+      const double xl = c->mx0[member] + c->ci[k] * dx, yl = c->my0[member] + c->cj[k] * dx;
+      if (x >= xl && x < xl + dx && y >= yl && y < yl + dx) {
+        found = k;
+        rx = (x - xl) / dx;
+        ry = (y - yl) / dx;
+      }
+    }
+    if (found < 0) return fail(SW_EINVAL, "point " + std::to_string(g) + " lies outside the member's mesh");
+    cell[g] = found;
+    for (int jy = 0; jy < c->N1; ++jy)
+      for (int jx = 0; jx < c->N1; ++jx) phi[(size_t)g * c->NP + jy * c->N1 + jx] = lag(xi, jx, rx) * lag(xi, jy, ry);
+  }
+  return SW_OK;
+}
+
 sw_status sw_cell_map(const sw_ctx* c, int32_t* member, int32_t* local) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   for (int k = 0; k < c->K; ++k) {

@@ -118,6 +118,10 @@ def test_observed_run_gradients_match_oracle():
     gauges = rng.uniform(0.1 * L, 0.9 * L, size=(10, 2))
     cells, phi = point_operator(o, gauges)
     nsteps = 11
+    s_ = gpu_from_oracle(o, b)
+    gc, gp = s_.locate_points(gauges)
+    assert np.array_equal(gc, cells) and np.abs(gp - phi).max() < 1e-14
+    s_.close()
     st0 = [x.clone() for x in o.state[:3]]
     truth = np.zeros((nsteps, len(gauges)))
     n0 = np.full(K, 0.0275) + rng.uniform(-0.005, 0.005, K)
@@ -157,13 +161,7 @@ def test_adjoint_128_full_size_central_differences():
     K, NP = s.n_cells, s.np_
     dtb = s.apply_operator(*state0)[4]
     dt = 0.9 * float(dtb.cpu()[0])      # fixed: 0.9 x the positivity bound at t = 0
-    # gauges: cell and basis values from the uniform grid
-    from oracle import tensor_basis
-    g = np.asarray(wl["gauges"])
-    dx = wl["mesh"]["dx0"]
-    ci, cj = np.floor(g[:, 0] / dx).astype(int), np.floor(g[:, 1] / dx).astype(int)
-    cells = cj * wl["mesh"]["nx0"] + ci
-    phi, _, _ = tensor_basis(2, g[:, 0] / dx - ci, g[:, 1] / dx - cj)
+    cells, phi = s.locate_points(wl["gauges"])
     obs = PointObservation(cells, phi, NP, "cuda:0")
     nsteps = wl["steps"]
     truth = observed_run(s, torch.as_tensor(wl["manning_truth"], device="cuda:0"),
