@@ -34,6 +34,47 @@ __device__ __forceinline__ int partner_i(int v) {
   else if constexpr (M == 8) return dpp_i<0x140>(v);
   else return __shfl_xor(v, M);
 }
+// Exact xor partners inside a row of 16 lanes: the row mirror pairs i with
+// 15 - i = i ^ 15, the half-row mirror i with i ^ 7 (within each 8 lanes).
+template <int XM>
+__device__ __forceinline__ double xpartner(double v) {
+  if constexpr (XM == 1) return dpp_d<0xB1>(v);
+  else if constexpr (XM == 2) return dpp_d<0x4E>(v);
+  else if constexpr (XM == 7) return dpp_d<0x141>(v);
+  else if constexpr (XM == 15) return dpp_d<0x140>(v);
+  else return __shfl_xor(v, XM);
+}
+
+// One halving step of a reduce-scatter: a lane whose decision bit is set keeps
+// the upper half of x[0..2H) and sends the lower half to its partner (which
+// keeps the lower half); the kept half, summed with what the partner sent,
+// moves to x[0..H).
+template <int XM, int H>
+__device__ __forceinline__ void rs_step(double* x, bool up) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = up ? x[i] : x[H + i];
+    const double keep = up ? x[H + i] : x[i];
+    x[i] = keep + xpartner<XM>(send);
+  }
+}
+
+// Sum of x[0..V) over the P lanes of a group (V a multiple of P), scattered:
+// afterwards lane l (index within the group) holds the totals of entries
+// l*(V/P) .. l*(V/P) + V/P - 1 in x[0..V/P).  The partners lane ^ 16, ^ 15,
+// ^ 7, ^ 2, ^ 1 are taken from the high decision bit down, so partners always
+// hold the same subset of entries and the pairings span all P lanes.
+template <int P, int V>
+__device__ __forceinline__ void reduce_scatter(double* x, int lane) {
+  static_assert(V % P == 0, "V must be a multiple of P");
+  // at decision bit b the kept half has V * 2^b / P entries
+  if constexpr (P >= 32) rs_step<16, V * 16 / P>(x, (lane >> 4) & 1);
+  if constexpr (P >= 16) rs_step<15, V * 8 / P>(x, (lane >> 3) & 1);
+  if constexpr (P >= 8) rs_step<7, V * 4 / P>(x, (lane >> 2) & 1);
+  if constexpr (P >= 4) rs_step<2, V * 2 / P>(x, (lane >> 1) & 1);
+  if constexpr (P >= 2) rs_step<1, V / P>(x, lane & 1);
+}
+
 // After the quad steps every lane of a quad holds the quad result, so the
 // mirrors combine whole quads (half rows) exactly like an xor butterfly.
 template <int P>
