@@ -6,11 +6,16 @@ zeta, qx, qy (and c with a tracer) times the stages taken, over the timed
 wall time), on the 256x256, r = 2, 16x16-sample beach dam break (SSP3), with
 every input resident in device memory before the timed region.
 
-One JSON line is printed.  Besides the metric it carries
+One JSON line is printed.  `value` comes from a timed region with no
+per-kernel events.  Besides the metric the line carries
   roofline:     the dominant kernel's algorithmic bytes and flops per launch
-                divided by its average launch time (HIP events recorded by
-                the library around its launches, on its stream, during the
-                timed region) against the MI355X peaks;
+                divided by its average launch time, from HIP events the
+                library records (on its stream, fence-free) around that
+                kernel's launches only, in a second timed pass over the same
+                steps from the same start; kernel_share comes from a third
+                pass with every kernel class timed;
+  ensemble:     ensemble_64, batched + graph-replayed vs one by one;
+  adjoint:      adjoint_128 gradient, backward vs forward time;
   cpu_baseline: the oracle timed on the host cores on a bounded window of
                 the same workload.
 """
@@ -238,6 +243,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=300, help="ensemble_64 steps per mode (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint_128 gradient timing")
+    ap.add_argument("--elem-wpb", type=int, default=0, help="wavefronts per workgroup of the fast element kernel "
+                    "(0: library default)")
     ap.add_argument("--only", choices=["ensemble", "adjoint"], default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -262,6 +269,8 @@ def main():
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
+    if args.elem_wpb:
+        s.set_workgroup(args.elem_wpb)
     stages = {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[wl["params"]["rk"]]
     r = int(wl["params"]["r"])
     S = int(wl["params"]["S"][0])
@@ -279,21 +288,47 @@ def main():
         for _ in range(2):
             bcopy.copy_(a)
         torch.cuda.synchronize()
-    s.profile(True)
-    s.kernel_time_reset()
-    torch.cuda.synchronize()
+    # timed region 1: the whole step with no per-kernel events -> value
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     ev0.record()
     s.run(args.steps)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    kt = s.kernel_times()
-    s.profile(False)
     s.sync()
     diag = s.diagnostics()
     value = dofs_stage * stages * args.steps / (ms * 1e-3)
+
+    # timed region 2: the same steps from the same start, HIP events (on the
+    # library's stream) around the dominant kernel's launches only
+    reset()
+    torch.cuda.synchronize()
+    s.profile(True, kinds=["element_stage"])
+    s.kernel_time_reset()
+    ev0.record()
+    s.run(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms2 = ev0.elapsed_time(ev1)
+    kt = s.kernel_times()
+    s.profile(False)
+
+    # region 3: every kernel class timed (shares of the step, informational)
+    reset()
+    n3 = min(args.steps, 100)
+    torch.cuda.synchronize()
+    s.profile(True)
+    s.kernel_time_reset()
+    ev0.record()
+    s.run(n3)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms3 = ev0.elapsed_time(ev1)
+    kt3 = s.kernel_times()
+    s.profile(False)
+    s.sync()
 
     # dominant kernel: the fast element kernel of stages 2..s
     k_ms, k_n = kt["element_stage"]
@@ -318,9 +353,10 @@ def main():
         roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(f_fp, 4))
     roof.update(traffic=traffic, kernel=f"k_elem<r={r},P={S},F_STAGE>",
-                launch_ms=round(avg_s * 1e3, 5), algo_bytes_per_launch=bytes_launch,
+                launch_ms=round(avg_s * 1e3, 5), launches=k_n, timed_region_ms=round(ms2, 3),
+                algo_bytes_per_launch=bytes_launch,
                 algo_flops_per_launch=flops_launch, hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4),
-                kernel_share={k: round(v[0] / ms, 4) for k, v in kt.items()})
+                kernel_share={k: round(v[0] / ms3, 4) for k, v in kt3.items()})
     line = dict(metric="FP64 DoF-updates/s per RK stage", value=value, unit="DoF-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",

@@ -235,13 +235,22 @@ sw_status sw_member_diagnostics(const sw_ctx *c, int32_t member, sw_diag *out_ho
  *   kind 2: fast element kernel of the final combination (+ next step's start)
  *   kind 3: face kernel
  *   kind 4: general element kernel (cells the fast kernel leaves, tracer runs).
- * sw_kernel_time_reset clears the totals. */
+ * sw_kernel_time_reset clears the totals.  on = 0: off; 1: every class;
+ * on = 1 | (mask << 1) with mask != 0: only the classes whose bit is set in
+ * mask (fewer events, less perturbation).  The events are timing-only (no
+ * system-scope fence at record). */
 sw_status sw_profile(sw_ctx *c, int32_t on);
 sw_status sw_kernel_time(sw_ctx *c, int32_t kind, double *ms_total, int64_t *launches);
 sw_status sw_kernel_time_reset(sw_ctx *c);
 
 /* Wait for the context's stream; reports SW_EDEVICE if a kernel flagged an error. */
 sw_status sw_sync(sw_ctx *c);
+
+/* Launch shape (results do not depend on it): wavefronts per workgroup
+ * (1, 2 or 4) of the fast element kernel (kernel 0) on one level (level < 0:
+ * all levels); a workgroup then holds wpb * 64 / P cells, P the power of two
+ * >= S_L.  Default 4.  SW_EINVAL for other values. */
+sw_status sw_set_workgroup(sw_ctx *c, int32_t level, int32_t kernel, int32_t wpb);
 
 /* ---- ensembles of independent members (not part of the paper's method) ----
  * sw_ens_create groups the members into batched contexts (sw_create_batch),

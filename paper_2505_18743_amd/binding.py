@@ -24,7 +24,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points"]
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points", "sw_set_workgroup"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -81,6 +81,7 @@ def load():
     L.sw_vjp_operator.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sw_step_record.argtypes = [vp, ctypes.c_double, vp]
     L.sw_locate_points.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.sw_set_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.sw_vjp_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
@@ -391,8 +392,17 @@ class Solver:
         _check(load().sw_vjp_step(self.h, _ptr(stages), float(t), float(dt), _ptr(state_bar), _ptr(n_bar),
                                   _ptr(db_bar)), "sw_vjp_step")
 
-    def profile(self, on=True):
-        _check(load().sw_profile(self.h, int(bool(on))), "sw_profile")
+    def set_workgroup(self, wpb, level=-1, kernel=0):
+        """Wavefronts per workgroup of the fast element kernel (1, 2 or 4)."""
+        _check(load().sw_set_workgroup(self.h, int(level), int(kernel), int(wpb)), "sw_set_workgroup")
+
+    def profile(self, on=True, kinds=None):
+        """Kernel timing on/off; kinds: names of KERNELS to time (default all)."""
+        v = int(bool(on))
+        if on and kinds:
+            mask = sum(1 << self.KERNELS.index(k) for k in kinds)
+            v = 1 | (mask << 1)
+        _check(load().sw_profile(self.h, v), "sw_profile")
 
     KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general")
 

@@ -14,6 +14,19 @@ namespace swk {
 hipError_t launch_stage_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_stage_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_stage_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_stage_scan_r1(int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_stage_scan_r2(int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_stage_scan_r3(int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
+
+hipError_t launch_stage_scan(int r, int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return launch_stage_scan_r1(P, mode, mode2, a, nblk, s);
+    case 2: return launch_stage_scan_r2(P, mode, mode2, a, nblk, s);
+    case 3: return launch_stage_scan_r3(P, mode, mode2, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
@@ -41,9 +54,9 @@ __global__ void k_min_all(const double*, int, double*);
 __global__ void k_diag_part_seg(const double*, const int8_t*, const int*, double*);
 __global__ void k_diag_seg(const double*, const int*, double*, double*, const double*);
 
-hipError_t launch_elem_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
-hipError_t launch_elem_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
-hipError_t launch_elem_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem_r1(int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem_r2(int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem_r3(int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_vjp_vol_r1(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
 hipError_t launch_vjp_vol_r2(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
 hipError_t launch_vjp_vol_r3(int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
@@ -60,12 +73,12 @@ hipError_t launch_vjp_vol(int r, int P, int mode, const VjpArgs& a, int nblk, hi
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+hipError_t launch_elem(int r, int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   switch (r) {
-    case 1: return launch_elem_r1(P, mode, a, nblk, s);
-    case 2: return launch_elem_r2(P, mode, a, nblk, s);
-    case 3: return launch_elem_r3(P, mode, a, nblk, s);
+    case 1: return launch_elem_r1(P, mode, wpb, a, nblk, s);
+    case 2: return launch_elem_r2(P, mode, wpb, a, nblk, s);
+    case 3: return launch_elem_r3(P, mode, wpb, a, nblk, s);
   }
   return hipErrorInvalidValue;
 }
@@ -225,7 +238,9 @@ struct LevelH {
   // face classes: direction (x: W/E, y: S/N) x (conforming or boundary, sub-face 0,
   // sub-face 1); the faces of one class touch disjoint (cell, dof) sets
   int cface0[6]{}, cnface[6]{}, cfnblk[6]{};
-  int nblk = 0;              // element-kernel blocks
+  int nblk = 0;              // general element-kernel blocks (one wavefront each)
+  int wpb = 1;               // wavefronts per workgroup of the fast element kernel
+  int8_t* d_wflag = nullptr;  // per wavefront (nblk): cells left to the general kernel
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
   LevelTabs tabs{};
@@ -272,6 +287,7 @@ struct sw_ctx {
   std::vector<void*> allocs;
   // kernel timing (sw_profile): events recorded around each launch group
   bool prof = false;
+  int prof_mask = 0x1F;      // kernel classes timed while profiling
   struct Ev { int kind; int nlaunch; hipEvent_t a, b; };
   std::vector<Ev> ev;
   double prof_ms[8]{};
@@ -301,9 +317,12 @@ struct sw_ctx {
     hipEvent_t a{}, b{};
     bool on = false;
     Scope(sw_ctx* c_, int k, int n_) : c(c_), kind(k), n(n_) {
-      if (!c->prof) return;
-      if (hipEventCreate(&a) != hipSuccess) return;
-      if (hipEventCreate(&b) != hipSuccess) {
+      if (!c->prof || !((c->prof_mask >> kind) & 1)) return;
+      // timing-only events: no system-scope fence (cache write-back) at record,
+      // so the measurement does not perturb the launches it brackets
+      const unsigned fl = hipEventDisableSystemFence;
+      if (hipEventCreateWithFlags(&a, fl) != hipSuccess) return;
+      if (hipEventCreateWithFlags(&b, fl) != hipSuccess) {
         (void)hipEventDestroy(a);
         return;
       }
@@ -323,6 +342,7 @@ constexpr int kNSlot = 5;   // residual slots: up to 4 stages + one for sw_apply
 constexpr int kApplySlot = 4;
 constexpr int kMDiag = 16;  // per-member diagnostics: D_* slots, [7] dt, [8] t
 constexpr int kFaceChunk = 1024, kCellChunk = 256;
+constexpr int kListGrid = 1024;   // workgroups of the general kernel walking the wavefront flags
 
 void tableau(int rk, int& s, double A[4][4], double b[4], double c[4]) {
   for (int i = 0; i < 4; ++i) {
@@ -500,6 +520,8 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.res = c->d_res;
   a.flag = c->d_flag;
   a.need = nullptr;
+  a.wflag = nullptr;
+  a.nwave = 0;
   a.cdiag = c->d_cdiag;
   a.diag_init = 0;
   a.allwet = c->d_allwet;
@@ -589,18 +611,34 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
     if (fast_ok) {
       sw_ctx::Scope sc(c, kind, 1);
       a.need = c->d_need;
-      HIPCHK(launch_elem(c->r, L.P, fmode, a, L.nblk, c->s));
+      a.wflag = L.d_wflag;
+      a.nwave = L.nblk;
+      const int cpb = L.wpb * kWave / L.P;
+      HIPCHK(launch_elem(c->r, L.P, fmode, L.wpb, a, (L.ncell + cpb - 1) / cpb, c->s));
     }
     StageArgs g = a;
     g.need = fast_ok ? c->d_need : nullptr;
-    if (gmode >= 0) {
-      sw_ctx::Scope sc(c, 4, 1);
-      HIPCHK(launch_stage(c->r, L.P, gmode, g, L.nblk, c->s));
-    }
-    if (gmode2 >= 0) {
-      sw_ctx::Scope sc(c, 4, 1);
-      g.slot = 0;
-      HIPCHK(launch_stage(c->r, L.P, gmode2, g, L.nblk, c->s));
+    g.wflag = nullptr;
+    g.nwave = 0;
+    if (fast_ok) {
+      // the wavefronts the fast kernel flagged, walked by a small grid (both
+      // modes in one launch)
+      if (gmode >= 0) {
+        sw_ctx::Scope sc(c, 4, 1);
+        g.wflag = L.d_wflag;
+        g.nwave = L.nblk;
+        HIPCHK(launch_stage_scan(c->r, L.P, gmode, gmode2, g, std::min(L.nblk, kListGrid), c->s));
+      }
+    } else {
+      if (gmode >= 0) {
+        sw_ctx::Scope sc(c, 4, 1);
+        HIPCHK(launch_stage(c->r, L.P, gmode, g, L.nblk, c->s));
+      }
+      if (gmode2 >= 0) {
+        sw_ctx::Scope sc(c, 4, 1);
+        g.slot = 0;
+        HIPCHK(launch_stage(c->r, L.P, gmode2, g, L.nblk, c->s));
+      }
     }
   }
   return SW_OK;
@@ -916,10 +954,13 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   }
   for (auto& L : c->lv) {
     sw_status st = build_tables(c, L);
+    if (st == SW_OK) st = c->alloc(&L.d_wflag, (size_t)std::max(L.nblk, 1));
     if (st != SW_OK) {
       delete c;
       return st;
     }
+    hipError_t e = hipMemset(L.d_wflag, 0, (size_t)std::max(L.nblk, 1));
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
   }
   std::vector<double> cw1(K), mtide(4 * (size_t)M), mcfl(M);
   for (int k = 0; k < K; ++k) cw1[k] = p->cfl_mode == 1 ? c->lv[c->lev[k]].w1 : 1.0;
@@ -1458,9 +1499,19 @@ sw_status sw_sync(sw_ctx* c) {
   return SW_OK;
 }
 
+sw_status sw_set_workgroup(sw_ctx* c, int32_t level, int32_t kernel, int32_t wpb) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (kernel != 0) return fail(SW_EINVAL, "kernel must be 0 (fast element kernel)");
+  if (wpb != 1 && wpb != 2 && wpb != 4) return fail(SW_EINVAL, "wavefronts per workgroup must be 1, 2 or 4");
+  for (auto& L : c->lv)
+    if (level < 0 || L.L == level) L.wpb = wpb;
+  return SW_OK;
+}
+
 sw_status sw_profile(sw_ctx* c, int32_t on) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   c->prof = on != 0;
+  c->prof_mask = on > 1 ? (on >> 1) & 0x1F : 0x1F;
   return SW_OK;
 }
 

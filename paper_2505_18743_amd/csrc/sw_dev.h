@@ -34,6 +34,14 @@ __device__ __forceinline__ int partner_i(int v) {
   else if constexpr (M == 8) return dpp_i<0x140>(v);
   else return __shfl_xor(v, M);
 }
+// Ordering point for LDS data exchanged inside one wavefront (the wave's LDS
+// operations complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exact xor partners inside a row of 16 lanes: the row mirror pairs i with
 // 15 - i = i ^ 15, the half-row mirror i with i ^ 7 (within each 8 lanes).
 template <int XM>

@@ -145,21 +145,39 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
       }
     lmax = fmax(lmax, lam);
   }
-  // finish the face integrals over the face's lanes and add them into the
-  // residual slot; faces of one launch touch disjoint (cell, dof) sets
+  // finish the face integrals over the face's lanes with a reduce-scatter
+  // (lane l ends up owning entries l*PER .. l*PER + PER - 1 of each side),
+  // then read all owned residual entries, add, and write them back; faces of
+  // one launch touch disjoint (cell, dof) sets
+  constexpr int NE = NQ * N1, NEP = ((NE + Q - 1) / Q) * Q, PER = NEP / Q;
   const size_t KN = (size_t)A.K * NP;
   double* rA = A.res + (size_t)A.slot * 4 * KN + (size_t)cA * NP;
   double* rB = A.res + (size_t)A.slot * 4 * KN + (size_t)cB * NP;
+  double xa[NEP], xb[NEP];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int i = 0; i < NEP; ++i) {
+    xa[i] = i < NE ? pA[i / N1][i % N1] : 0.0;
+    xb[i] = i < NE ? pB[i / N1][i % N1] : 0.0;
+  }
+  reduce_scatter<Q, NEP>(xa, lane);
+  reduce_scatter<Q, NEP>(xb, lane);
+  double* pa[PER];
+  double* pb[PER];
+  double oa[PER], ob[PER];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      const double va = gsum<Q>(pA[q][k]);
-      const double vb = gsum<Q>(pB[q][k]);
-      const int ia = q * N1 + k;
-      if (q < nq && act && (ia % Q) == lane) rA[(size_t)q * KN + row_dof<R>(sA, k)] += va;
-      if (q < nq && act && !bnd && ((ia + 1) % Q) == lane) rB[(size_t)q * KN + row_dof<R>(sB, k)] += vb;
-    }
+  for (int e = 0; e < PER; ++e) {
+    const int ia = lane * PER + e;
+    const int iq = ia < NE ? ia / N1 : 0, ik = ia < NE ? ia % N1 : 0;
+    pa[e] = rA + (size_t)iq * KN + row_dof<R>(sA, ik);
+    pb[e] = rB + (size_t)iq * KN + row_dof<R>(sB, ik);
+    oa[e] = *pa[e];      // in range for every lane (clamped entry); used only if owned
+    ob[e] = *pb[e];
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int ia = lane * PER + e;
+    if (act && ia < NE) *pa[e] = oa[e] + xa[e];
+    if (act && !bnd && ia < NE) *pb[e] = ob[e] + xb[e];
   }
   // positivity time-step bound (Prop. 3.2): w J_K / (lambda l_Gamma) on both sides
   lmax = gmin<Q>(-lmax);

@@ -57,6 +57,8 @@ struct StageArgs {
   int8_t* flag;          // [K] current degree (r or 0)
   int8_t* need;          // [K] cells left to the general kernel (fast kernel writes,
                          //     general kernel reads: only flagged cells are processed)
+  int8_t* wflag;         // [nwave] per wavefront of the level (64/P cells): 1 if a cell is flagged
+  int nwave;
   double* cdiag;         // [K][D_NSLOT] per-cell diagnostics of the current step
   int diag_init;         // 1: first solve of the step initialises cdiag
   int8_t* allwet;        // [K] zeta^n wet at every sample node
@@ -144,7 +146,8 @@ hipError_t launch_vjp_face(int r, const VjpFaceArgs& a, int nblk, hipStream_t s)
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
-hipError_t launch_elem(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_stage_scan(int r, int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_elem(int r, int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s);
 
 // context hooks used by the ensemble driver

@@ -16,15 +16,26 @@ static hipError_t stage_p(int mode, const StageArgs& a, int nblk, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int P>
-static hipError_t elem_p(int mode, const StageArgs& a, int nblk, hipStream_t s) {
+template <int P, int WPB>
+static hipError_t elem_pw(int mode, const StageArgs& a, int nblk, hipStream_t s) {
   switch (mode) {
-    case F_START: hipLaunchKernelGGL((k_elem<2, P, F_START>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    case F_STAGE: hipLaunchKernelGGL((k_elem<2, P, F_STAGE>), dim3(nblk), dim3(kWave), 0, s, a); break;
-    case F_FINAL: hipLaunchKernelGGL((k_elem<2, P, F_FINAL>), dim3(nblk), dim3(kWave), 0, s, a); break;
+    case F_START: hipLaunchKernelGGL((k_elem<2, P, F_START, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
+    case F_STAGE: hipLaunchKernelGGL((k_elem<2, P, F_STAGE, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
+    case F_FINAL: hipLaunchKernelGGL((k_elem<2, P, F_FINAL, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// wavefronts per workgroup: 1, 2 or 4 (cells per workgroup = wpb * 64 / P)
+template <int P>
+static hipError_t elem_p(int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (wpb) {
+    case 1: return elem_pw<P, 1>(mode, a, nblk, s);
+    case 2: return elem_pw<P, 2>(mode, a, nblk, s);
+    case 4: return elem_pw<P, 4>(mode, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stage_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
@@ -37,12 +48,35 @@ hipError_t launch_stage_r2(int P, int mode, const StageArgs& a, int nblk, hipStr
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_elem_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+template <int P>
+static hipError_t stage_scan_p(int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s) {
+  if (mode == M_START && mode2 < 0)
+    hipLaunchKernelGGL((k_stage_scan<2, P, M_START, -1>), dim3(nblk), dim3(kWave), 0, s, a);
+  else if (mode == M_STAGE && mode2 < 0)
+    hipLaunchKernelGGL((k_stage_scan<2, P, M_STAGE, -1>), dim3(nblk), dim3(kWave), 0, s, a);
+  else if (mode == M_FINAL && mode2 == M_START)
+    hipLaunchKernelGGL((k_stage_scan<2, P, M_FINAL, M_START>), dim3(nblk), dim3(kWave), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_scan_r2(int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s) {
   switch (P) {
-    case 4: return elem_p<4>(mode, a, nblk, s);
-    case 8: return elem_p<8>(mode, a, nblk, s);
-    case 16: return elem_p<16>(mode, a, nblk, s);
-    case 32: return elem_p<32>(mode, a, nblk, s);
+    case 4: return stage_scan_p<4>(mode, mode2, a, nblk, s);
+    case 8: return stage_scan_p<8>(mode, mode2, a, nblk, s);
+    case 16: return stage_scan_p<16>(mode, mode2, a, nblk, s);
+    case 32: return stage_scan_p<32>(mode, mode2, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_elem_r2(int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s) {
+  switch (P) {
+    case 4: return elem_p<4>(mode, wpb, a, nblk, s);
+    case 8: return elem_p<8>(mode, wpb, a, nblk, s);
+    case 16: return elem_p<16>(mode, wpb, a, nblk, s);
+    case 32: return elem_p<32>(mode, wpb, a, nblk, s);
   }
   return hipErrorInvalidValue;
 }
