@@ -125,6 +125,7 @@ def ensemble_bench(steps, warmup, device):
     from workloads import workload
     mem = workload("ensemble_64")
     ens, inputs = setup_ensemble(mem, device)
+    tuned = ens.autotune(steps=3)      # launch shape per degree class (state restored)
     stages = 3
     dofs = sum(3 * (w["params"]["r"] + 1) ** 2 * len(w["mesh"]["level"]) for w in mem)
     cells = sum(len(w["mesh"]["level"]) for w in mem)
@@ -152,6 +153,10 @@ def ensemble_bench(steps, warmup, device):
         res[mode] = timed(lambda: ens.run(steps, graph=graph))
         ens.sync()
     ones = [member_solver(ens, inputs, mem, m, device) for m in range(len(mem))]
+    for m, o in enumerate(ones):         # the same launch shapes one by one
+        t = tuned[ens.where[m][0]]
+        o.set_workgroup(t["elem_waves_per_workgroup"], kernel=0)
+        o.set_workgroup(t["face_lanes"], kernel=1)
     etas = []
     for m in range(len(mem)):
         b, i = ens.where[m]
@@ -175,7 +180,7 @@ def ensemble_bench(steps, warmup, device):
                 ms_per_step=res["graph"] / steps * 1e3, eager_ms_per_step=res["eager"] / steps * 1e3,
                 one_by_one_ms_per_step=res["one_by_one"] / steps * 1e3,
                 speedup_vs_one_by_one=res["one_by_one"] / res["graph"],
-                graph_speedup_vs_eager=res["eager"] / res["graph"])
+                graph_speedup_vs_eager=res["eager"] / res["graph"], autotuned=tuned)
 
 
 def adjoint_bench(device, reps=3):

@@ -246,11 +246,24 @@ sw_status sw_kernel_time_reset(sw_ctx *c);
 /* Wait for the context's stream; reports SW_EDEVICE if a kernel flagged an error. */
 sw_status sw_sync(sw_ctx *c);
 
-/* Launch shape (results do not depend on it): wavefronts per workgroup
- * (1, 2 or 4) of the fast element kernel (kernel 0) on one level (level < 0:
- * all levels); a workgroup then holds wpb * 64 / P cells, P the power of two
- * >= S_L.  Default 4.  SW_EINVAL for other values. */
-sw_status sw_set_workgroup(sw_ctx *c, int32_t level, int32_t kernel, int32_t wpb);
+/* Launch shape on one level (level < 0: all levels).  The element kernel's
+ * shape does not change results; the face kernel's changes only the order in
+ * which a face's node contributions are summed (rounding).  Kernel 0, the fast
+ * element kernel: value = wavefronts per
+ * workgroup (1, 2 or 4; a workgroup holds value * 64 / P cells, P the power
+ * of two >= S_L; default 1); kernel 1, the face kernel: value = lanes per
+ * face (2, 4 or 8; the S_L face nodes are split over them; default 4).
+ * SW_EINVAL for other values.  sw_get_workgroup reads the current value. */
+sw_status sw_set_workgroup(sw_ctx *c, int32_t level, int32_t kernel, int32_t value);
+sw_status sw_get_workgroup(const sw_ctx *c, int32_t level, int32_t kernel, int32_t *value);
+/* Autotuner of the launch shape: times `steps` steps (after one untimed step)
+ * with every pair (fast-kernel wavefronts per workgroup in {1, 2, 4}) x (face
+ * lanes per face in {2, 4, 8}) on the context's current state, keeps the
+ * fastest pair on every level and puts the state, degrees, times and time
+ * steps back as they were (the next step recomputes its start-of-step terms;
+ * results are unchanged).  dt as sw_step.  Allocates a snapshot of the state
+ * while it runs.  Outputs (host, may be NULL): the chosen pair.  Synchronises. */
+sw_status sw_autotune(sw_ctx *c, int32_t steps, double dt, int32_t *wpb_host, int32_t *lanes_host);
 
 /* ---- ensembles of independent members (not part of the paper's method) ----
  * sw_ens_create groups the members into batched contexts (sw_create_batch),
@@ -275,6 +288,12 @@ sw_status sw_ens_member(const sw_ens *e, int32_t m, int32_t *batch, int32_t *ind
 sw_status sw_ens_run(sw_ens *e, int32_t n_steps, double dt, int32_t use_graph);
 /* Wait for all work of the ensemble; SW_EDEVICE as sw_sync. */
 sw_status sw_ens_sync(sw_ens *e);
+/* Launch-shape autotuner of every batch (sw_autotune with `steps` timed
+ * steps, on the batch's current state, which is restored).  cache_path (may
+ * be NULL or empty): a text file of "<class> <wavefronts per workgroup>
+ * <lanes per face>" lines, class "r<r>_S<S>"; classes found there are applied
+ * without timing, new ones are timed and written back.  Synchronises. */
+sw_status sw_ens_autotune(sw_ens *e, int32_t steps, const char *cache_path);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points", "sw_set_workgroup"]
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
+           "sw_ens_autotune"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -82,6 +83,10 @@ def load():
     L.sw_step_record.argtypes = [vp, ctypes.c_double, vp]
     L.sw_locate_points.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.sw_set_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.sw_get_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.sw_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32)]
+    L.sw_ens_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p]
     L.sw_vjp_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
@@ -392,9 +397,22 @@ class Solver:
         _check(load().sw_vjp_step(self.h, _ptr(stages), float(t), float(dt), _ptr(state_bar), _ptr(n_bar),
                                   _ptr(db_bar)), "sw_vjp_step")
 
-    def set_workgroup(self, wpb, level=-1, kernel=0):
-        """Wavefronts per workgroup of the fast element kernel (1, 2 or 4)."""
-        _check(load().sw_set_workgroup(self.h, int(level), int(kernel), int(wpb)), "sw_set_workgroup")
+    def set_workgroup(self, value, level=-1, kernel=0):
+        """Launch shape: kernel 0 = fast element kernel, value = wavefronts
+        per workgroup (1, 2, 4); kernel 1 = face kernel, value = lanes per face
+        (2, 4, 8)."""
+        _check(load().sw_set_workgroup(self.h, int(level), int(kernel), int(value)), "sw_set_workgroup")
+
+    def get_workgroup(self, level=0, kernel=0):
+        v = ctypes.c_int32()
+        _check(load().sw_get_workgroup(self.h, int(level), int(kernel), ctypes.byref(v)), "sw_get_workgroup")
+        return v.value
+
+    def autotune(self, steps=8, dt=0.0):
+        """Time every launch shape on the current state, keep the fastest."""
+        w, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().sw_autotune(self.h, int(steps), float(dt), ctypes.byref(w), ctypes.byref(q)), "sw_autotune")
+        return dict(elem_waves_per_workgroup=w.value, face_lanes=q.value)
 
     def profile(self, on=True, kinds=None):
         """Kernel timing on/off; kinds: names of KERNELS to time (default all)."""
@@ -520,6 +538,12 @@ class Ensemble:
 
     def run(self, n, dt=0.0, graph=True):
         _check(load().sw_ens_run(self.h, int(n), float(dt), int(bool(graph))), "sw_ens_run")
+
+    def autotune(self, steps=8, cache=None):
+        """Launch-shape autotuner of every batch; returns the chosen shapes."""
+        _check(load().sw_ens_autotune(self.h, int(steps), (cache or "").encode()), "sw_ens_autotune")
+        return [dict(r=s.params["r"], elem_waves_per_workgroup=s.get_workgroup(0, 0),
+                     face_lanes=s.get_workgroup(0, 1)) for s in self.batches]
 
     def sync(self):
         _check(load().sw_ens_sync(self.h), "sw_ens_sync")

@@ -240,6 +240,7 @@ struct LevelH {
   int cface0[6]{}, cnface[6]{}, cfnblk[6]{};
   int nblk = 0;              // general element-kernel blocks (one wavefront each)
   int wpb = 1;               // wavefronts per workgroup of the fast element kernel
+  int face_q = kFaceLanes;   // lanes per face of the face kernel
   int8_t* d_wflag = nullptr;  // per wavefront (nblk): cells left to the general kernel
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
@@ -580,7 +581,8 @@ sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, con
       if (L.cnface[k] == 0) continue;
       FaceArgs fa = face_args(c, L, k, st, cstage, slot);
       if (mt_override) fa.mt = mt_override;
-      HIPCHK(launch_face(c->r, L.P, fa, L.cfnblk[k], c->s));
+      const int fpb = kWave / L.face_q;
+      HIPCHK(launch_face(c->r, L.face_q, fa, (L.cnface[k] + fpb - 1) / fpb, c->s));
     }
   return SW_OK;
 }
@@ -1499,13 +1501,119 @@ sw_status sw_sync(sw_ctx* c) {
   return SW_OK;
 }
 
-sw_status sw_set_workgroup(sw_ctx* c, int32_t level, int32_t kernel, int32_t wpb) {
+sw_status sw_set_workgroup(sw_ctx* c, int32_t level, int32_t kernel, int32_t value) {
   if (!c) return fail(SW_EINVAL, "NULL context");
-  if (kernel != 0) return fail(SW_EINVAL, "kernel must be 0 (fast element kernel)");
-  if (wpb != 1 && wpb != 2 && wpb != 4) return fail(SW_EINVAL, "wavefronts per workgroup must be 1, 2 or 4");
+  if (kernel == 0) {
+    if (value != 1 && value != 2 && value != 4) return fail(SW_EINVAL, "wavefronts per workgroup must be 1, 2 or 4");
+  } else if (kernel == 1) {
+    if (value != 2 && value != 4 && value != 8) return fail(SW_EINVAL, "lanes per face must be 2, 4 or 8");
+  } else {
+    return fail(SW_EINVAL, "kernel must be 0 (fast element kernel) or 1 (face kernel)");
+  }
   for (auto& L : c->lv)
-    if (level < 0 || L.L == level) L.wpb = wpb;
+    if (level < 0 || L.L == level) (kernel == 0 ? L.wpb : L.face_q) = value;
   return SW_OK;
+}
+
+sw_status sw_autotune(sw_ctx* c, int32_t steps, double dt, int32_t* wpb_out, int32_t* q_out) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (steps < 1 || steps > 1000) return fail(SW_EINVAL, "steps must be 1..1000");
+  sw_status st = need_bathy(c);
+  if (st != SW_OK) return st;
+  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_autotune cannot run inside an open step");
+  // snapshot of everything a step changes that the next step reads
+  const size_t KN = (size_t)c->K * c->NP;
+  std::vector<void*> keep;
+  auto dalloc = [&](size_t bytes) -> void* {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+    keep.push_back(q);
+    return q;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(c->s);
+    for (void* q : keep) (void)hipFree(q);
+  };
+  double* snap = (double*)dalloc(sizeof(double) * (4 * KN + 18 * (size_t)c->M));
+  int8_t* sflag = (int8_t*)dalloc((size_t)c->K);
+  if (!snap || !sflag) {
+    cleanup();
+    return fail(SW_ENOMEM, "sw_autotune: no memory for the state snapshot");
+  }
+  auto copy = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->s);
+  };
+  hipError_t e = hipSuccess;
+  for (int f = 0; f < 4 && e == hipSuccess; ++f) e = copy(snap + f * KN, c->d_sn[f], sizeof(double) * KN);
+  if (e == hipSuccess) e = copy(snap + 4 * KN, c->d_mt, sizeof(double) * c->M);
+  if (e == hipSuccess) e = copy(snap + 4 * KN + c->M, c->d_mdt, sizeof(double) * c->M);
+  if (e == hipSuccess) e = copy(snap + 4 * KN + 2 * c->M, c->d_mdiag, sizeof(double) * kMDiag * c->M);
+  if (e == hipSuccess) e = copy(sflag, c->d_flag, (size_t)c->K);
+  auto restore = [&]() {
+    hipError_t r = hipSuccess;
+    for (int f = 0; f < 4 && r == hipSuccess; ++f) r = copy(c->d_sn[f], snap + f * KN, sizeof(double) * KN);
+    if (r == hipSuccess) r = copy(c->d_mt, snap + 4 * KN, sizeof(double) * c->M);
+    if (r == hipSuccess) r = copy(c->d_mdt, snap + 4 * KN + c->M, sizeof(double) * c->M);
+    if (r == hipSuccess) r = copy(c->d_mdiag, snap + 4 * KN + 2 * c->M, sizeof(double) * kMDiag * c->M);
+    if (r == hipSuccess) r = copy(c->d_flag, sflag, (size_t)c->K);
+    c->start_ready = false;
+    c->stage_done = 0;
+    return r;
+  };
+  const int64_t nstep0 = c->nstep;
+  const bool prof0 = c->prof;
+  c->prof = false;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  const int wpbs[3] = {1, 2, 4}, qs[3] = {2, 4, 8};
+  int bw = c->lv[0].wpb, bq = c->lv[0].face_q;
+  float best = 1e30f;
+  for (int iw = 0; iw < 3 && e == hipSuccess && st == SW_OK; ++iw)
+    for (int iq = 0; iq < 3 && e == hipSuccess && st == SW_OK; ++iq) {
+      for (auto& L : c->lv) {
+        L.wpb = wpbs[iw];
+        L.face_q = qs[iq];
+      }
+      if ((e = restore()) != hipSuccess) break;
+      if ((st = sw_step(c, dt)) != SW_OK) break;   // start-of-step terms and warm caches
+      if ((e = hipEventRecord(ea, c->s)) != hipSuccess) break;
+      if ((st = sw_run(c, steps, dt)) != SW_OK) break;
+      if ((e = hipEventRecord(eb, c->s)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(eb)) != hipSuccess) break;
+      float ms = 0.0f;
+      if ((e = hipEventElapsedTime(&ms, ea, eb)) != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        bw = wpbs[iw];
+        bq = qs[iq];
+      }
+    }
+  for (auto& L : c->lv) {
+    L.wpb = bw;
+    L.face_q = bq;
+  }
+  if (e == hipSuccess && st == SW_OK) e = restore();
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  cleanup();
+  c->nstep = nstep0;
+  c->prof = prof0;
+  if (st != SW_OK) return st;
+  if (e != hipSuccess) return fail(SW_EHIP, std::string("sw_autotune: ") + hipGetErrorString(e));
+  if (wpb_out) *wpb_out = bw;
+  if (q_out) *q_out = bq;
+  return SW_OK;
+}
+
+sw_status sw_get_workgroup(const sw_ctx* c, int32_t level, int32_t kernel, int32_t* value) {
+  if (!c || !value) return fail(SW_EINVAL, "NULL argument");
+  for (auto& L : c->lv)
+    if (L.L == level) {
+      *value = kernel == 0 ? L.wpb : L.face_q;
+      return SW_OK;
+    }
+  return fail(SW_EINVAL, "no such level");
 }
 
 sw_status sw_profile(sw_ctx* c, int32_t on) {
@@ -1565,6 +1673,10 @@ hipStream_t ctx_swap_stream(sw_ctx* c, hipStream_t s) {
 }
 hipStream_t ctx_stream(const sw_ctx* c) { return c->s; }
 int ctx_cells(const sw_ctx* c) { return c->K; }
+void ctx_class(const sw_ctx* c, int* r, int* S0) {
+  *r = c->r;
+  *S0 = c->lv.empty() ? 0 : c->lv[0].S;
+}
 int api_fail(int status, const char* msg) { return (int)fail((sw_status)status, msg); }
 }  // namespace swk
 

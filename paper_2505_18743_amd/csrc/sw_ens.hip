@@ -7,6 +7,7 @@
 // step.  The batches run on their own streams, forked from and joined to the
 // caller's stream, so that batches of different degree overlap on the device.
 // A step of all batches can be captured once into a hipGraph and replayed.
+#include <cstdio>
 #include <map>
 #include <string>
 #include <tuple>
@@ -239,6 +240,49 @@ sw_status sw_ens_run(sw_ens* e, int32_t n_steps, double dt, int32_t use_graph) {
   EHIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
   for (auto c : e->batch) ctx_set_steps(c, ctx_steps(c) + (n_steps - done));
   e->graph_launches += n_steps - done;
+  return SW_OK;
+}
+
+sw_status sw_ens_autotune(sw_ens* e, int32_t steps, const char* cache_path) {
+  if (!e) return efail(SW_EINVAL, "NULL ensemble");
+  // cache: one line per batch class, "<key> <wavefronts per workgroup> <lanes per face>"
+  std::map<std::string, std::pair<int, int>> cache;
+  if (cache_path && cache_path[0]) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char key[128];
+      int w = 0, q = 0;
+      while (fscanf(f, "%127s %d %d", key, &w, &q) == 3) cache[key] = {w, q};
+      fclose(f);
+    }
+  }
+  bool changed = false;
+  for (size_t b = 0; b < e->batch.size(); ++b) {
+    sw_ctx* c = e->batch[b];
+    int32_t S0 = 0, r = 0;
+    ctx_class(c, &r, &S0);
+    const std::string key = "r" + std::to_string(r) + "_S" + std::to_string(S0);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      sw_status st = sw_set_workgroup(c, -1, 0, it->second.first);
+      if (st == SW_OK) st = sw_set_workgroup(c, -1, 1, it->second.second);
+      if (st != SW_OK) return st;
+      continue;
+    }
+    int32_t w = 0, q = 0;
+    sw_status st = sw_autotune(c, steps, 0.0, &w, &q);
+    if (st != SW_OK) return st;
+    cache[key] = {w, q};
+    changed = true;
+  }
+  e->drop_graph();   // a captured step holds the old launch shapes
+  if (changed && cache_path && cache_path[0]) {
+    if (FILE* f = fopen(cache_path, "w")) {
+      for (auto& kv : cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+      fclose(f);
+    } else {
+      return efail(SW_EINVAL, std::string("cannot write the autotune cache ") + cache_path);
+    }
+  }
   return SW_OK;
 }
 

@@ -1,6 +1,6 @@
 // Face kernel of the sub-grid DG shallow-water operator (gfx950, FP64).
 //
-// One face per group of kFaceLanes lanes; the lanes split the face nodes (the
+// One face per group of Q lanes (2, 4 or 8); the lanes split the face nodes (the
 // fine or equal side's closed S-point rule, whose nodes are the boundary row of
 // that side's sample grid).  At each node both traces come from the (r+1)
 // nodal coefficients of the face row (GLL support points include the element
@@ -190,20 +190,30 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
   if (fv && lane == 0) A.fdt[f] = bnd_dt;
 }
 
-template <int R>
-static hipError_t face_r(int P, const FaceArgs& a, int nblk, hipStream_t s) {
-  (void)P;
-  if (a.tracer) hipLaunchKernelGGL((k_face<R, kFaceLanes, 4>), dim3(nblk), dim3(kWave), 0, s, a);
-  else hipLaunchKernelGGL((k_face<R, kFaceLanes, 3>), dim3(nblk), dim3(kWave), 0, s, a);
+template <int R, int Q>
+static hipError_t face_rq(const FaceArgs& a, int nblk, hipStream_t s) {
+  if (a.tracer) hipLaunchKernelGGL((k_face<R, Q, 4>), dim3(nblk), dim3(kWave), 0, s, a);
+  else hipLaunchKernelGGL((k_face<R, Q, 3>), dim3(nblk), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s) {
+template <int R>
+static hipError_t face_r(int q, const FaceArgs& a, int nblk, hipStream_t s) {
+  switch (q) {
+    case 2: return face_rq<R, 2>(a, nblk, s);
+    case 4: return face_rq<R, 4>(a, nblk, s);
+    case 8: return face_rq<R, 8>(a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// q lanes per face (2, 4 or 8): 64 / q faces per workgroup
+hipError_t launch_face(int r, int q, const FaceArgs& a, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   switch (r) {
-    case 1: return face_r<1>(P, a, nblk, s);
-    case 2: return face_r<2>(P, a, nblk, s);
-    case 3: return face_r<3>(P, a, nblk, s);
+    case 1: return face_r<1>(q, a, nblk, s);
+    case 2: return face_r<2>(q, a, nblk, s);
+    case 3: return face_r<3>(q, a, nblk, s);
   }
   return hipErrorInvalidValue;
 }

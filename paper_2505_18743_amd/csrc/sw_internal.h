@@ -7,7 +7,7 @@
 namespace swk {
 
 constexpr int kWave = 64;
-constexpr int kFaceLanes = 4;   // lanes per face in the face kernel
+constexpr int kFaceLanes = 4;   // lanes per face of the face VJP kernel (default of the face kernel)
 
 // ---- stage-kernel modes ---------------------------------------------------
 enum Mode : int {
@@ -148,7 +148,7 @@ hipError_t launch_vjp_face(int r, const VjpFaceArgs& a, int nblk, hipStream_t s)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_stage_scan(int r, int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem(int r, int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
-hipError_t launch_face(int r, int P, const FaceArgs& a, int nblk, hipStream_t s);
+hipError_t launch_face(int r, int q, const FaceArgs& a, int nblk, hipStream_t s);
 
 // context hooks used by the ensemble driver
 }  // namespace swk
@@ -161,6 +161,7 @@ bool ctx_set_prof(sw_ctx* c, bool on);   // returns the previous setting
 hipStream_t ctx_swap_stream(sw_ctx* c, hipStream_t s);   // returns the previous stream
 hipStream_t ctx_stream(const sw_ctx* c);
 int ctx_cells(const sw_ctx* c);
+void ctx_class(const sw_ctx* c, int* r, int* S0);   // degree and level-0 sample count
 int api_fail(int status, const char* msg);   // records msg for sw_last_error, returns status
 
 inline int lanes_for(int S) {

@@ -214,3 +214,32 @@ def test_full_ensemble_64_sampled_members():
         say(f"  member {m} N={sizes[m]} r={mem[m]['params']['r']} equal, t={d['t']:.3f}")
         one.close()
     ens.close()
+
+
+def test_ensemble_autotune_and_cache(tmp_path):
+    say("case: ensemble autotune with a cache file, 6 small members")
+    mem = small_members()
+    ens, inputs = setup_ensemble(mem)
+    cache = str(tmp_path / "tune.txt")
+    chosen = ens.autotune(steps=2, cache=cache)
+    say(f"  chosen {chosen}")
+    lines = open(cache).read().split("\n")
+    assert len([l for l in lines if l.strip()]) == len(ens.batches)
+    # a second ensemble picks the shapes up from the cache without timing
+    ens2, _ = setup_ensemble(mem)
+    again = ens2.autotune(steps=2, cache=cache)
+    assert again == chosen
+    # tuned ensemble vs one-by-one runs (rounding only: face-sum order)
+    ens.run(6, graph=True)
+    ens.sync()
+    for m, w in enumerate(mem):
+        one = member_solver(ens, inputs, mem, m)
+        one.run(6)
+        one.sync()
+        a, b = ens.get_state(m), one.get_state()
+        for f in range(3):
+            d = float((a[f] - b[f]).abs().max()) / max(float(b[f].abs().max()), 1e-300)
+            assert d < 1e-10, (m, f, d)
+        one.close()
+    ens.close()
+    ens2.close()
