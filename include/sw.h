@@ -207,7 +207,9 @@ sw_status sw_vjp_operator(sw_ctx *c, const double *eta, const double *qx, const 
                           double *qy_b, double *n_bar, double *db_bar);
 /* sw_step_record: one step with the fixed dt > 0 (as sw_step) that also
  * stores its stage states u^(1) = u^n, u^(2), ..., u^(s) into stages (device
- * [s][3][n_dofs]: zeta, qx, qy per stage).
+ * [s][3][n_dofs]: zeta, qx, qy per stage) and, when end is not NULL, the
+ * flow u^(n+1) of the final combination into end (device [3][n_dofs]), as it
+ * stands before the next step's degree decision and remap (Sec. 3.3).
  * sw_vjp_step: adjoint of that step in the all-wet regime (every rule node wet
  * in every stage, every cell of degree r, no tracer), where the step is the
  * explicit map u^(l) = u^n + dt M^-1 sum_m a_lm R(u^(m)) of Sec. 3.1 with M the
@@ -218,9 +220,26 @@ sw_status sw_vjp_operator(sw_ctx *c, const double *eta, const double *qx, const 
  * accumulated.  t is the step's start time.  A stage state outside the regime
  * makes the next sw_sync report SW_EDEVICE (code 4).  Uses the context's
  * residual storage: the next step recomputes its start-of-step terms. */
-sw_status sw_step_record(sw_ctx *c, double dt, double *stages_dev);
+sw_status sw_step_record(sw_ctx *c, double dt, double *stages_dev, double *end_dev);
 sw_status sw_vjp_step(sw_ctx *c, const double *stages_dev, double t, double dt, double *state_bar,
                       double *n_bar, double *db_bar);
+
+/* sw_tracer_step: advances the context's tracer by one recorded step with
+ * the flow given, not solved: the tracer solve of eq:algebraic_concentration
+ * with H(zeta^(l)) and the tracer residual R (eq:r_concentration) of every
+ * stage, where zeta^(l), q^(l) are read from stages (l = 2..s, as
+ * sw_step_record writes them) and the final flow from end; the Newton and
+ * discharge solves are skipped.  dt is the recorded step's dt (> 0).  The
+ * context's flow must equal the recorded step's start state: set it with
+ * sw_set_state (and sw_set_time) where the recording started, then call
+ * sw_tracer_step once per recorded step in order; each call leaves the
+ * context where the coupled step would (flow = end after the next step's
+ * degree decision, tracer advanced, time + dt).  Recorded by a context with
+ * a tracer, the replayed tracer equals the coupled run's bit for bit; a
+ * record of a flow-only context may differ from it by rounding (its element
+ * kernel sums in another order).  Requires params.tracer; the buffers are
+ * read only. */
+sw_status sw_tracer_step(sw_ctx *c, const double *stages_dev, const double *end_dev, double dt);
 
 /* Diagnostics of the last step (host output).  Synchronises.  In a batched
  * context dt and t are member 0's; masses and counts are summed, extrema

@@ -24,7 +24,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_locate_points", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
            "sw_ens_autotune"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -80,7 +80,8 @@ def load():
     L.sw_ens_run.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
     L.sw_ens_sync.argtypes = [vp]
     L.sw_vjp_operator.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.sw_step_record.argtypes = [vp, ctypes.c_double, vp]
+    L.sw_step_record.argtypes = [vp, ctypes.c_double, vp, vp]
+    L.sw_tracer_step.argtypes = [vp, vp, vp, ctypes.c_double]
     L.sw_locate_points.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.sw_set_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.sw_get_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -382,11 +383,25 @@ class Solver:
     def n_stages(self):
         return {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[self.params.get("rk", "ssp3")]
 
-    def step_record(self, dt, stages):
-        """One fixed-dt step storing its stage states into `stages` [s, 3, n_dofs]."""
-        if stages.numel() != self.n_stages() * 3 * self.n_dofs or not stages.is_contiguous():
-            raise ValueError("stages must be a contiguous [s, 3, n_dofs] float64 tensor")
-        _check(load().sw_step_record(self.h, float(dt), _ptr(stages)), "sw_step_record")
+    def _flow_buf(self, x, n, what):
+        if (not torch.is_tensor(x) or x.numel() != n * 3 * self.n_dofs or not x.is_contiguous()
+                or x.dtype != torch.float64 or x.device.type != "cuda"):
+            raise ValueError(f"{what} must be a contiguous float64 device tensor of {n} x 3 x n_dofs")
+
+    def step_record(self, dt, stages, end=None):
+        """One fixed-dt step storing its stage states into `stages` [s, 3, n_dofs]
+        and, if given, the final combination's flow into `end` [3, n_dofs]."""
+        self._flow_buf(stages, self.n_stages(), "stages")
+        if end is not None:
+            self._flow_buf(end, 1, "end")
+        _check(load().sw_step_record(self.h, float(dt), _ptr(stages), _ptr(end)),
+               "sw_step_record")
+
+    def tracer_step(self, stages, end, dt):
+        """Advance the tracer by one recorded step (flow from `stages`, `end`)."""
+        self._flow_buf(stages, self.n_stages(), "stages")
+        self._flow_buf(end, 1, "end")
+        _check(load().sw_tracer_step(self.h, _ptr(stages), _ptr(end), float(dt)), "sw_tracer_step")
 
     def vjp_step(self, stages, t, dt, state_bar, n_bar, db_bar):
         """Adjoint of one recorded step: state_bar [3, n_dofs] updated in place

@@ -281,6 +281,8 @@ struct sw_ctx {
   double* d_fdb = nullptr;
   int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
+  const double* rp[3] = {nullptr, nullptr, nullptr};   // tracer replay: recorded flow of the current stage
+  double* rec[3] = {nullptr, nullptr, nullptr};        // record of the final combination's flow
   bool fixed_dt = false;
   bool bathy_set = false;
   int stage_done = 0;      // stages completed in the current step (0: no step open)
@@ -523,6 +525,10 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.need = nullptr;
   a.wflag = nullptr;
   a.nwave = 0;
+  for (int f = 0; f < 3; ++f) {
+    a.replay[f] = c->rp[f];
+    a.rec_end[f] = c->rec[f];
+  }
   a.cdiag = c->d_cdiag;
   a.diag_init = 0;
   a.allwet = c->d_allwet;
@@ -1321,7 +1327,7 @@ sw_status sw_step(sw_ctx* c, double dt) {
   return sw_step_end(c);
 }
 
-sw_status sw_step_record(sw_ctx* c, double dt, double* stages) {
+sw_status sw_step_record(sw_ctx* c, double dt, double* stages, double* end) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (!stages) return fail(SW_EINVAL, "stages must be non-NULL");
   if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_step_record needs a fixed dt > 0");
@@ -1341,7 +1347,35 @@ sw_status sw_step_record(sw_ctx* c, double dt, double* stages) {
     if ((st = sw_rk_stage(c, l)) != SW_OK) return st;
     if ((st = save(c->d_ss, l - 1)) != SW_OK) return st;
   }
-  return sw_step_end(c);
+  const size_t KN3 = KN;
+  for (int f = 0; f < 3; ++f) c->rec[f] = end ? end + f * KN3 : nullptr;
+  st = sw_step_end(c);
+  for (int f = 0; f < 3; ++f) c->rec[f] = nullptr;
+  return st;
+}
+
+sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, double dt) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!c->p.tracer) return fail(SW_EINVAL, "sw_tracer_step needs a context with a tracer");
+  if (!stages || !end) return fail(SW_EINVAL, "stages and end must be non-NULL");
+  if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_tracer_step needs the recorded step's dt > 0");
+  const size_t KN = (size_t)c->K * c->NP;
+  auto point = [&](const double* base) {
+    for (int f = 0; f < 3; ++f) c->rp[f] = base ? base + f * KN : nullptr;
+  };
+  point(nullptr);
+  sw_status st = sw_step_begin(c, dt);
+  if (st != SW_OK) return st;
+  for (int l = 2; l <= c->ns && st == SW_OK; ++l) {
+    point(stages + (size_t)(l - 1) * 3 * KN);
+    st = sw_rk_stage(c, l);
+  }
+  if (st == SW_OK) {
+    point(end);
+    st = sw_step_end(c);
+  }
+  point(nullptr);
+  return st;
 }
 
 }  // extern "C"

@@ -59,6 +59,9 @@ struct StageArgs {
                          //     general kernel reads: only flagged cells are processed)
   int8_t* wflag;         // [nwave] per wavefront of the level (64/P cells): 1 if a cell is flagged
   int nwave;
+  const double* replay[3];   // tracer replay: recorded zeta, qx, qy of this stage (else NULL)
+  double* rec_end[3];        // final combination: copy of the new zeta, qx, qy before any
+                             // degree change of the next step (else NULL)
   double* cdiag;         // [K][D_NSLOT] per-cell diagnostics of the current step
   int diag_init;         // 1: first solve of the step initialises cdiag
   int8_t* allwet;        // [K] zeta^n wet at every sample node
