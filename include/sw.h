@@ -60,7 +60,12 @@ enum { SW_BC_WALL = 0,      /* ghost mirrors the normal discharge               
        SW_BC_ELEV = 1,      /* ghost imposes zeta = A sin(2 pi t / T + phase),     */
                             /* extrapolates q, takes c_in on inflow                */
        SW_BC_OPEN = 2,      /* ghost copies the interior state                     */
-       SW_BC_PERIODIC = 3 };/* opposite sides are joined (must come in pairs)      */
+       SW_BC_PERIODIC = 3,  /* opposite sides are joined (must come in pairs)      */
+       SW_BC_STATE = 4,     /* ghost is a given (zeta, q, c) per face node (an     */
+                            /* exact state at a supercritical inflow, Sec. 4.4)    */
+       SW_BC_DISCHARGE = 5 };/* ghost takes a given q per face node, extrapolates  */
+                            /* zeta, takes the given c where q.n < 0 (the inflow   */
+                            /* discharge of the channel case, Sec. 4.3)            */
 
 enum { SW_RULE_EQ = 0,      /* closed equispaced (composite trapezoid) rule         */
        SW_RULE_GLL = 1 };   /* Gauss-Legendre-Lobatto rule                         */
@@ -140,6 +145,23 @@ sw_status sw_cell_map(const sw_ctx *c, int32_t *member_host, int32_t *local_host
  * for a point outside the member's mesh (cells are half-open [x, x+dx)). */
 sw_status sw_locate_points(const sw_ctx *c, int32_t member, int32_t n, const double *xy_host, int32_t *cell_host,
                            double *phi_host);
+
+/* Given boundary data of the SW_BC_STATE and SW_BC_DISCHARGE sides.  Their
+ * face nodes (the S_L nodes of the cell's rule along each boundary face of
+ * those sides, faces in the library's order, nodes ascending along the face)
+ * number n_nodes; sw_boundary_nodes writes the count and, where not NULL, the
+ * coordinates xy_host [n_nodes][2] (member coordinates) and member_host
+ * [n_nodes].  sw_set_boundary_state copies ghost_dev (device [4][n_nodes]:
+ * zeta, qx, qy, c at each node; a discharge side reads qx, qy and c) into the
+ * context, where it holds until the next call: it is the ghost of every stage
+ * of the following steps (a time-dependent state is sampled by the caller
+ * between steps).  Steps, sw_apply_operator and the adjoint calls return
+ * SW_EINVAL on a mesh with such sides until it has been called once;
+ * sw_set_boundary_state returns SW_EINVAL on a mesh without them.  Boundary
+ * faces use the interior flux formulas with this ghost (Sec. 3.2: jumps and
+ * averages on boundary faces are one-sided). */
+sw_status sw_boundary_nodes(const sw_ctx *c, int64_t *n_nodes, double *xy_host, int32_t *member_host);
+sw_status sw_set_boundary_state(sw_ctx *c, const double *ghost_dev);
 
 /* Sizes: cells, sample nodes (sum of S_L^2), nodal values per field. */
 sw_status sw_counts(const sw_ctx *c, int64_t *n_cells, int64_t *n_vol_nodes, int64_t *n_dofs);

@@ -35,7 +35,12 @@ ambiguous or garbled (each one is also listed in the design notes):
     (r+1)^2, Table 1 / Sec. 3.3).
   * Boundary faces use a ghost state and the interior flux formulas
     (walls mirror the normal discharge; an elevation boundary imposes
-    zeta, extrapolates q and takes the inflow tracer value on inflow).
+    zeta, extrapolates q and takes the inflow tracer value on inflow; a
+    state boundary imposes a given (zeta, q, c) at every face node, as for an
+    exact solution at a supercritical inflow; a discharge boundary imposes a
+    given q, extrapolates zeta and takes the given c where q.n < 0, as for
+    the subcritical inflow of a channel).  Given boundary data are held
+    constant over a step.
   * Rusanov speed uses the unreconstructed depths (eq:lxf_parameter).
   * Friction is explicit, added to the discharge residual, with the
     desingularised depth (eq:discharge_rhs_implicit with an explicit RK).
@@ -68,6 +73,7 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 OPPOSITE = {WEST: EAST, EAST: WEST, SOUTH: NORTH, NORTH: SOUTH}
 NORMAL = {WEST: (-1.0, 0.0), EAST: (1.0, 0.0), SOUTH: (0.0, -1.0), NORTH: (0.0, 1.0)}
 BC_WALL, BC_ELEV, BC_OPEN, BC_PERIODIC = "wall", "elev", "open", "periodic"
+BC_STATE, BC_DISCHARGE = "state", "discharge"
 
 
 # ---------------------------------------------------------------------------
@@ -530,7 +536,9 @@ class Oracle:
             _, wh = rule_for(self.p.rule, lv.S)
             k = torch.as_tensor(lst, dtype=torch.long)
             kind = m.bc[side]
-            self.bface_groups.append(dict(side=side, lv=lv, k=k, pos=self.cell_level_pos[k],
+            xs = m.x0 + (m.ii[lst][:, None] + X[None, :]) * lv.dx
+            ys = m.y0 + (m.jj[lst][:, None] + Y[None, :]) * lv.dx
+            self.bface_groups.append(dict(side=side, lv=lv, k=k, pos=self.cell_level_pos[k], xy=(xs, ys),
                                           row=torch.as_tensor(self._row_nodes(side, lv.S)),
                                           v=torch.as_tensor(v), wl=torch.as_tensor(wh) * lv.dx,
                                           normal=NORMAL[side], kind=kind))
@@ -621,7 +629,7 @@ class Oracle:
             lv = bg["lv"]
             zbA = self.zb_eff(lv, dbed)[bg["pos"]][:, bg["row"]]
             trA = [s[k] @ v.T for s in state]
-            trB = self._ghost(bg["kind"], trA, nx, ny, t)
+            trB = self._ghost(bg["kind"], trA, nx, ny, t, bg.get("given"))
             fl = self._flux(trA, trB, zbA, zbA, nx, ny)
             wl = bg["wl"]
             F = F.index_add(0, k, -(wl * fl["mass"]) @ v)
@@ -636,8 +644,24 @@ class Oracle:
                 dtb = torch.minimum(dtb, bnd.min())
         return F, Gx, Gy, R, dtb
 
-    def _ghost(self, kind, tr, nx, ny, t):
+    def set_boundary_state(self, fn):
+        """Boundary data of the state and discharge sides: fn(x, y) -> (zeta, qx,
+        qy, c) at the face nodes (arrays of the shape of x)."""
+        for bg in self.bface_groups:
+            if bg["kind"] in (BC_STATE, BC_DISCHARGE):
+                vals = fn(*bg["xy"])
+                bg["given"] = [torch.as_tensor(np.broadcast_to(np.asarray(v, dtype=np.float64), bg["xy"][0].shape).copy())
+                               for v in vals]
+
+    def _ghost(self, kind, tr, nx, ny, t, given=None):
         zeta, qx, qy, c = tr
+        if kind in (BC_STATE, BC_DISCHARGE) and given is None:
+            raise ValueError("boundary data of a state or discharge side are not set")
+        if kind == BC_STATE:
+            return list(given)
+        if kind == BC_DISCHARGE:
+            inflow = (given[1] * nx + given[2] * ny) < 0
+            return [zeta, given[1], given[2], torch.where(inflow, given[3], c)]
         if kind == BC_WALL:
             qn = qx * nx + qy * ny
             return [zeta, qx - 2.0 * qn * nx, qy - 2.0 * qn * ny, c]

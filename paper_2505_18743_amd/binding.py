@@ -14,7 +14,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libswdg.so")
 
-BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3}
+BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3, "state": 4, "discharge": 5}
 RULE = {"eq": 0, "gll": 1}
 RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3}
 
@@ -24,7 +24,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
-           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
+           "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
            "sw_ens_autotune"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -83,6 +83,8 @@ def load():
     L.sw_step_record.argtypes = [vp, ctypes.c_double, vp, vp]
     L.sw_tracer_step.argtypes = [vp, vp, vp, ctypes.c_double]
     L.sw_locate_points.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.sw_boundary_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp]
+    L.sw_set_boundary_state.argtypes = [vp, vp]
     L.sw_set_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.sw_get_workgroup.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.sw_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
@@ -274,6 +276,30 @@ class Solver:
                                        cell.ctypes.data_as(ctypes.c_void_p), phi.ctypes.data_as(ctypes.c_void_p)),
                "sw_locate_points")
         return cell, phi
+
+    def boundary_nodes(self):
+        """(xy [n, 2], member [n]) of the face nodes of the state and discharge sides."""
+        n = ctypes.c_int64(0)
+        _check(load().sw_boundary_nodes(self.h, ctypes.byref(n), None, None), "sw_boundary_nodes")
+        xy = np.zeros((n.value, 2))
+        mem = np.zeros(n.value, dtype=np.int32)
+        if n.value:
+            _check(load().sw_boundary_nodes(self.h, ctypes.byref(n), xy.ctypes.data_as(ctypes.c_void_p),
+                                            mem.ctypes.data_as(ctypes.c_void_p)), "sw_boundary_nodes")
+        return xy, mem
+
+    def set_boundary_state(self, given):
+        """Given boundary data: a [4, n] array (zeta, qx, qy, c per boundary
+        node) or a function fn(x, y) -> (zeta, qx, qy, c) sampled at the nodes."""
+        if callable(given):
+            xy, _ = self.boundary_nodes()
+            vals = given(xy[:, 0], xy[:, 1])
+            given = np.stack([np.broadcast_to(np.asarray(v, dtype=np.float64), (len(xy),)) for v in vals])
+        n = ctypes.c_int64(0)
+        _check(load().sw_boundary_nodes(self.h, ctypes.byref(n), None, None), "sw_boundary_nodes")
+        t = self._dev(given, 4 * n.value)
+        _check(load().sw_set_boundary_state(self.h, _ptr(t)), "sw_set_boundary_state")
+        self._ghost = t        # kept alive until the copy has run
 
     def member_diagnostics(self, m):
         d = SwDiag()

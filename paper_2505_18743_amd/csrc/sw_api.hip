@@ -279,6 +279,13 @@ struct sw_ctx {
   // adjoint: per-face bed-offset parts [F][2] and, per cell, the list of its
   // entries in that array (CSR, face order)
   double* d_fdb = nullptr;
+  // given boundary data (state and discharge sides): per face the offset of its
+  // nodes in the [4][ng] array (-1: none), faces carrying data in face order
+  int* d_gof = nullptr;
+  double* d_ghost = nullptr;
+  int64_t ng = 0;
+  std::vector<int> gface;
+  bool ghost_set = false;
   int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
   const double* rp[3] = {nullptr, nullptr, nullptr};   // tracer replay: recorded flow of the current stage
@@ -573,6 +580,9 @@ FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st,
   a.g = c->p.g;
   a.eps = c->p.eps;
   a.tracer = c->p.tracer ? 1 : 0;
+  a.gof = c->d_gof;
+  a.ghost = c->d_ghost;
+  a.ng = c->ng;
   return a;
 }
 
@@ -684,6 +694,15 @@ sw_status need_bathy(const sw_ctx* c) {
   return SW_OK;
 }
 
+// bathymetry and, with state or discharge sides, their boundary data
+sw_status need_inputs(const sw_ctx* c) {
+  sw_status st = need_bathy(c);
+  if (st != SW_OK) return st;
+  if (c->ng > 0 && !c->ghost_set)
+    return fail(SW_EINVAL, "the mesh has state or discharge sides: call sw_set_boundary_state first");
+  return SW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -721,7 +740,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     if (md.n_cells < 1 || !md.level || !md.i || !md.j) return fail(SW_EINVAL, "empty mesh");
     if (md.nx0 < 1 || md.ny0 < 1 || !(md.dx0 > 0.0)) return fail(SW_EINVAL, "bad coarse grid");
     for (int sd = 0; sd < 4; ++sd)
-      if (md.bc[sd] < 0 || md.bc[sd] > 3) return fail(SW_EINVAL, "bad boundary kind");
+      if (md.bc[sd] < 0 || md.bc[sd] > SW_BC_DISCHARGE) return fail(SW_EINVAL, "bad boundary kind");
     if ((md.bc[0] == SW_BC_PERIODIC) != (md.bc[1] == SW_BC_PERIODIC) ||
         (md.bc[2] == SW_BC_PERIODIC) != (md.bc[3] == SW_BC_PERIODIC))
       return fail(SW_EINVAL, "periodic boundaries must come in pairs");
@@ -877,6 +896,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     fB[f] = h.b;
     fmem[f] = c->cmem[h.a];
     meta[f] = h.sa | (h.sb << 2) | ((h.sub + 1) << 4) | (h.bnd << 6) | (h.bc << 8);
+    if (h.bnd && (h.bc == SW_BC_STATE || h.bc == SW_BC_DISCHARGE)) c->gface.push_back(f);
     // every cell side carries one face, or two sub-faces on a coarse side
     if (used[(size_t)h.a * 8 + h.sa * 2]++) return bail(SW_EINVAL, "two faces on one cell side");
     if (!h.bnd && used[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)]++)
@@ -958,6 +978,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_fdb, (size_t)2 * c->F);
     ALLOC(c->d_cfoff, (size_t)K + 1);
     ALLOC(c->d_cfent, (size_t)2 * c->F);
+    ALLOC(c->d_gof, c->F);
 #undef ALLOC
   }
   for (auto& L : c->lv) {
@@ -989,6 +1010,26 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     hipError_t e_ = hipMemset(dst, 0, bytes);                                                  \
     if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e_)); \
   } while (0)
+  {
+    // node offsets of the faces with given boundary data (S nodes of the face's level)
+    std::vector<int> gof(c->F, -1);
+    int64_t o = 0;
+    for (int f : c->gface) {
+      gof[f] = (int)o;
+      o += c->lv[c->lev[fA[f]]].S;
+    }
+    if (o > INT32_MAX / 4) return bail(SW_EINVAL, "too many boundary data nodes");
+    c->ng = o;
+    H2D(c->d_gof, gof.data(), c->F);
+    if (c->ng > 0) {
+      sw_status st = c->alloc(&c->d_ghost, (size_t)4 * c->ng);
+      if (st != SW_OK) {
+        delete c;
+        return st;
+      }
+      ZERO(c->d_ghost, (size_t)4 * c->ng * sizeof(double));
+    }
+  }
   H2D(c->d_fA, fA.data(), c->F);
   H2D(c->d_fB, fB.data(), c->F);
   H2D(c->d_meta, meta.data(), c->F);
@@ -1105,6 +1146,45 @@ sw_status sw_locate_points(const sw_ctx* c, int32_t member, int32_t n, const dou
     for (int jy = 0; jy < c->N1; ++jy)
       for (int jx = 0; jx < c->N1; ++jx) phi[(size_t)g * c->NP + jy * c->N1 + jx] = lag(xi, jx, rx) * lag(xi, jy, ry);
   }
+  return SW_OK;
+}
+
+sw_status sw_boundary_nodes(const sw_ctx* c, int64_t* n_nodes, double* xy, int32_t* member) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (n_nodes) *n_nodes = c->ng;
+  if (!xy && !member) return SW_OK;
+  std::vector<int> fA(c->F), meta(c->F);
+  if (hipMemcpy(fA.data(), c->d_fA, c->F * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(meta.data(), c->d_meta, c->F * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SW_EHIP, "hipMemcpy of the face list failed");
+  int64_t o = 0;
+  for (int f : c->gface) {
+    const int k = fA[f], side = meta[f] & 3, m = c->cmem[k];
+    const LevelH& L = c->lv[c->lev[k]];
+    const double dx = c->cdx[k];
+    for (int al = 0; al < L.S; ++al, ++o) {
+      // face nodes in the order of the side's rule (ascending along the face)
+      const double X = side == 0 ? 0.0 : side == 1 ? 1.0 : L.xh[al];
+      const double Y = side == 2 ? 0.0 : side == 3 ? 1.0 : L.xh[al];
+      if (xy) {
+        xy[2 * o + 0] = c->mx0[m] + (c->ci[k] + X) * dx;
+        xy[2 * o + 1] = c->my0[m] + (c->cj[k] + Y) * dx;
+      }
+      if (member) member[o] = m;
+    }
+  }
+  return SW_OK;
+}
+
+sw_status sw_set_boundary_state(sw_ctx* c, const double* ghost) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (c->ng == 0) return fail(SW_EINVAL, "the mesh has no state or discharge side");
+  if (!ghost) return fail(SW_EINVAL, "ghost must be non-NULL");
+  const size_t n = (size_t)4 * c->ng;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->s, ghost, c->d_ghost, n);
+  HIPCHK(hipGetLastError());
+  c->ghost_set = true;
+  c->start_ready = false;
   return SW_OK;
 }
 
@@ -1227,7 +1307,7 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (!eta || !qx || !qy || !F || !Gx || !Gy) return fail(SW_EINVAL, "state and residual pointers must be non-NULL");
   if (c->p.tracer && (!tr || !R)) return fail(SW_EINVAL, "tracer and R are required with a tracer");
-  sw_status st = need_bathy(c);
+  sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_apply_operator cannot run inside an open step");
   // the elevation boundary is evaluated at t (stage offset 0)
@@ -1265,7 +1345,7 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
 
 sw_status sw_step_begin(sw_ctx* c, double dt) {
   if (!c) return fail(SW_EINVAL, "NULL context");
-  sw_status st = need_bathy(c);
+  sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   if (c->stage_done != 0) return fail(SW_EINVAL, "a step is already open (call sw_rk_stage / sw_step_end)");
   c->fixed_dt = dt > 0.0;
@@ -1425,6 +1505,9 @@ sw_status vjp_faces(sw_ctx* c, const double* const* u, const double* const* rb, 
       a.fl = L.tabs.fl;
       a.w = L.tabs.w;
       a.mtide = c->d_mtide;
+      a.gof = c->d_gof;
+      a.ghost = c->d_ghost;
+      a.ng = c->ng;
       a.tt = tt;
       a.err = c->d_err;
       a.g = c->p.g;
@@ -1447,7 +1530,7 @@ sw_status sw_vjp_operator(sw_ctx* c, const double* eta, const double* qx, const 
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (!eta || !qx || !qy || !Fb || !Gxb || !Gyb || !eta_b || !qx_b || !qy_b || !n_bar || !db_bar)
     return fail(SW_EINVAL, "all arrays of sw_vjp_operator must be non-NULL");
-  sw_status st = need_bathy(c);
+  sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   const unsigned nbk = (unsigned)((c->K + 255) / 256);
   hipLaunchKernelGGL(k_fill, dim3(nbk), dim3(256), 0, c->s, n_bar, (size_t)c->K, 0.0);
@@ -1477,7 +1560,7 @@ sw_status sw_vjp_step(sw_ctx* c, const double* stages, double t, double dt, doub
   if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_vjp_step needs the step's fixed dt > 0");
   if (c->p.tracer) return fail(SW_EINVAL, "the step adjoint covers runs without a tracer");
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_vjp_step cannot run inside an open step");
-  sw_status st = need_bathy(c);
+  sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   const size_t KN = (size_t)c->K * c->NP;
   const int ns = c->ns;
@@ -1552,7 +1635,7 @@ sw_status sw_set_workgroup(sw_ctx* c, int32_t level, int32_t kernel, int32_t val
 sw_status sw_autotune(sw_ctx* c, int32_t steps, double dt, int32_t* wpb_out, int32_t* q_out) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (steps < 1 || steps > 1000) return fail(SW_EINVAL, "steps must be 1..1000");
-  sw_status st = need_bathy(c);
+  sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_autotune cannot run inside an open step");
   // snapshot of everything a step changes that the next step reads

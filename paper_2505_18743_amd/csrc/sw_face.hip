@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
   int cA = A.fA[f], cB = A.fB[f];
   const int meta = A.meta[f];
   const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
-  const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 3;
+  const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 7;
   const bool ok = (cA >= 0 && cA < A.K) && (bnd || (cB >= 0 && cB < A.K));
   if (!ok && fv && lane == 0) atomicOr(A.err, 2);
   const bool act = fv && ok;
@@ -58,6 +58,13 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
   const double dxA = A.cdx[cA];
   const double* tB0 = A.fl + (size_t)(sub < 0 ? 0 : 1 + sub) * S * N1;
   double zeta_b = 0.0, c_in = 0.0;
+  // given boundary data (state: all of zeta, q, c; discharge: q and inflow c)
+  const double* gd = nullptr;
+  if (bnd && (bc == 4 || bc == 5)) {
+    const int go = A.gof[f];
+    if (go >= 0 && go + S <= A.ng) gd = A.ghost + go;
+    else if (fv && lane == 0) atomicOr(A.err, 2);
+  }
   if (bnd && bc == 1) {
     const int m = A.cmem[cA];
     const double* td = A.mtide + (size_t)m * 4;
@@ -107,6 +114,14 @@ __global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
         vB[1] = vA[1];
         vB[2] = vA[2];
         vB[3] = (vA[1] * nx + vA[2] * ny) < 0.0 ? c_in : vA[3];
+      } else if (bc == 4 && gd) {   // given state
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vB[q] = gd[(size_t)q * A.ng + al];
+      } else if (bc == 5 && gd) {   // given discharge, zeta extrapolated, c given on inflow
+        vB[0] = vA[0];
+        vB[1] = gd[(size_t)1 * A.ng + al];
+        vB[2] = gd[(size_t)2 * A.ng + al];
+        vB[3] = (vB[1] * nx + vB[2] * ny) < 0.0 ? gd[(size_t)3 * A.ng + al] : vA[3];
       } else {                  // open: copy
 #pragma unroll
         for (int q = 0; q < 4; ++q) vB[q] = vA[q];

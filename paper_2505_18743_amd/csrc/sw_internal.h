@@ -77,7 +77,7 @@ struct FaceArgs {
   int face0, nface, K, S;
   const int* fA;
   const int* fB;
-  const int* meta;       // sideA | sideB<<2 | (sub+1)<<4 | boundary<<6 | bc<<8
+  const int* meta;       // sideA | sideB<<2 | (sub+1)<<4 | boundary<<6 | bc<<8 (3 bits)
   const double* zf;      // group block [nface][2][S]
   const double* st[4];
   double* res;           // [NS][4][K][NP] residual slots
@@ -92,6 +92,9 @@ struct FaceArgs {
   const double* mtide;   // [M][4] tide amplitude, period, phase, inflow tracer
   double cstage;         // c_l of the stage
   double* fdt;           // [F] positivity bound of each face
+  const int* gof;        // [F] node offset of the face's given boundary data, -1: none
+  const double* ghost;   // [4][ng] given zeta, qx, qy, c at those nodes
+  int64_t ng;
   int* err;
   double g, eps;
   int tracer;
@@ -139,6 +142,9 @@ struct VjpFaceArgs {
   const double* fl;      // [3][S][N1]
   const double* w;       // [S]
   const double* mtide;   // [M][4]
+  const int* gof;        // [F] as in FaceArgs
+  const double* ghost;   // [4][ng]
+  int64_t ng;
   double tt;             // time of the stage (elevation boundary)
   int* err;
   double g, eps;

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kWave) void k_vjp_face(VjpFaceArgs A) {
   int cA = A.fA[f], cB = A.fB[f];
   const int meta = A.meta[f];
   const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
-  const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 3;
+  const int bnd = (meta >> 6) & 1, bc = (meta >> 8) & 7;
   const bool ok = (cA >= 0 && cA < A.K) && (bnd || (cB >= 0 && cB < A.K));
   if (!ok && fv && lane == 0) atomicOr(A.err, 2);
   const bool act = fv && ok;
@@ -167,6 +167,12 @@ __global__ __launch_bounds__(kWave) void k_vjp_face(VjpFaceArgs A) {
   if (bnd && bc == 1) {
     const double* td = A.mtide + (size_t)A.cmem[cA] * 4;
     zeta_b = td[0] * sin(6.283185307179586 * A.tt / td[1] + td[2]);
+  }
+  const double* gd = nullptr;
+  if (bnd && (bc == 4 || bc == 5)) {
+    const int go = A.gof[f];
+    if (go >= 0 && go + S <= A.ng) gd = A.ghost + go;
+    else if (fv && lane == 0) atomicOr(A.err, 2);
   }
 
   double gAk[3][N1], gBk[3][N1];
@@ -213,6 +219,13 @@ __global__ __launch_bounds__(kWave) void k_vjp_face(VjpFaceArgs A) {
         vB[0] = zeta_b;
         vB[1] = vA[1];
         vB[2] = vA[2];
+      } else if (bc == 4 && gd) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) vB[q] = gd[(size_t)q * A.ng + al];
+      } else if (bc == 5 && gd) {
+        vB[0] = vA[0];
+        vB[1] = gd[(size_t)1 * A.ng + al];
+        vB[2] = gd[(size_t)2 * A.ng + al];
       } else {
         vB[0] = vA[0];
         vB[1] = vA[1];
@@ -231,6 +244,10 @@ __global__ __launch_bounds__(kWave) void k_vjp_face(VjpFaceArgs A) {
       } else if (bc == 1) {
         gA[1] += gB[1];
         gA[2] += gB[2];
+      } else if (bc == 4) {
+        // given state: no dependence on the interior
+      } else if (bc == 5) {
+        gA[0] += gB[0];
       } else {
         gA[0] += gB[0];
         gA[1] += gB[1];
