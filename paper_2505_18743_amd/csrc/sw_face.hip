@@ -22,7 +22,7 @@ __device__ __forceinline__ int row_dof(int side, int k) {
 }
 
 template <int R, int Q, int NQ>
-__global__ __launch_bounds__(kWave) void k_face(FaceArgs A) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 3 : 2))) void k_face(FaceArgs A) {
   constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
   const int S = A.S;
   const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
