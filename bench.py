@@ -14,6 +14,8 @@ per-kernel events.  Besides the metric the line carries
                 kernel's launches only, in a second timed pass over the same
                 steps from the same start; kernel_share comes from a third
                 pass with every kernel class timed;
+  quadtree:     the 2-level quadtree with tracer, tide and hanging faces
+                (about 120k leaves, r = 3): DoF-updates/s of its coupled step;
   ensemble:     ensemble_64, batched + graph-replayed vs one by one;
   adjoint:      adjoint_128 gradient, backward vs forward time;
   cpu_baseline: the oracle timed on the host cores on a bounded window of
@@ -114,6 +116,46 @@ def cpu_baseline(name, seconds):
     return dict(value=dofs * stages * n / el, unit="DoF-updates/s", cores=torch.get_num_threads(), kind="oracle",
                 sample=f"oracle on a {o.m.K}-cell window (24x12) of {name}, {n} SSP3 steps after 1 warm-up step, "
                        f"{el:.1f} s")
+
+
+def quadtree_bench(steps, warmup, device):
+    """The 2-level quadtree with about 120k leaves (r=3, 32/16/8 samples per
+    level, tracer, tide, hanging faces): DoF-updates/s of the coupled step
+    (zeta, qx, qy and the tracer), and the kernel classes' shares."""
+    import torch
+    from workloads import workload
+    wl = workload("tidal_quadtree_r3")
+    s, reset, _ = setup(wl, device)
+    stages = {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[wl["params"]["rk"]]
+    dofs_stage = 4 * (int(wl["params"]["r"]) + 1) ** 2 * s.n_cells
+    s.run(warmup)
+    s.sync()
+    reset()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    s.run(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    diag = s.diagnostics()
+    reset()
+    torch.cuda.synchronize()
+    s.profile(True)
+    s.kernel_time_reset()
+    ev0.record()
+    s.run(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms2 = ev0.elapsed_time(ev1)
+    kt = s.kernel_times()
+    s.profile(False)
+    s.close()
+    return dict(workload="tidal_quadtree_r3", cells=s.n_cells, steps=steps, ms_per_step=ms / steps,
+                value=dofs_stage * stages * steps / (ms * 1e-3), unit="DoF-updates/s",
+                fields=4, r0_cells=diag["n_r0_cells"], max_newton_it=diag["max_newton_it"],
+                kernel_share={k: round(v[0] / ms2, 4) for k, v in kt.items()})
 
 
 def ensemble_bench(steps, warmup, device):
@@ -248,9 +290,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=300, help="ensemble_64 steps per mode (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint_128 gradient timing")
+    ap.add_argument("--qt-steps", type=int, default=100, help="tidal_quadtree_r3 steps (0: skip)")
     ap.add_argument("--elem-wpb", type=int, default=0, help="wavefronts per workgroup of the fast element kernel "
                     "(0: library default)")
-    ap.add_argument("--only", choices=["ensemble", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree"], default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
@@ -271,6 +314,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_bench(dev)), flush=True)
+        return
+    if args.only == "quadtree":
+        print(json.dumps(quadtree_bench(args.qt_steps, 3, dev)), flush=True)
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
@@ -370,6 +416,8 @@ def main():
                 roofline=roof)
     line["config"]["max_newton_it"] = diag["max_newton_it"]
     line["config"]["r0_cells"] = diag["n_r0_cells"]
+    if args.qt_steps > 0:
+        line["quadtree"] = quadtree_bench(args.qt_steps, 3, dev)
     if args.ens_steps > 0:
         line["ensemble"] = ensemble_bench(args.ens_steps, 3, dev)
     if not args.no_adjoint:

@@ -463,7 +463,7 @@ class Solver:
             v = 1 | (mask << 1)
         _check(load().sw_profile(self.h, v), "sw_profile")
 
-    KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general")
+    KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general", "element_tracer")
 
     def kernel_times(self):
         """{kernel class: (total ms, launches)} accumulated while profiling."""

@@ -48,6 +48,7 @@ __global__ void k_fill(double*, size_t, double);
 __global__ void k_fill8(int8_t*, size_t, int8_t);
 __global__ void k_copy(const double*, double*, size_t);
 __global__ void k_fill_n(double*, int, double);
+__global__ void k_copy8(const int8_t*, int8_t*, size_t);
 __global__ void k_minred_seg(const double*, const int*, double*);
 __global__ void k_dt_seg(const double*, const int*, const double*, double*);
 __global__ void k_min_all(const double*, int, double*);
@@ -79,6 +80,20 @@ hipError_t launch_elem(int r, int P, int mode, int wpb, const StageArgs& a, int 
     case 1: return launch_elem_r1(P, mode, wpb, a, nblk, s);
     case 2: return launch_elem_r2(P, mode, wpb, a, nblk, s);
     case 3: return launch_elem_r3(P, mode, wpb, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_trc_r1(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_trc_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_trc_r3(int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
+
+hipError_t launch_trc(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return launch_trc_r1(P, mode, a, nblk, s);
+    case 2: return launch_trc_r2(P, mode, a, nblk, s);
+    case 3: return launch_trc_r3(P, mode, a, nblk, s);
   }
   return hipErrorInvalidValue;
 }
@@ -275,7 +290,7 @@ struct sw_ctx {
   double *d_fdt = nullptr, *d_part = nullptr;
   int *d_fch = nullptr, *d_fch_m0 = nullptr, *d_cch = nullptr, *d_cch_m0 = nullptr;
   int nfch = 0, ncch = 0;
-  int8_t *d_flag = nullptr, *d_allwet = nullptr, *d_need = nullptr;
+  int8_t *d_flag = nullptr, *d_allwet = nullptr, *d_need = nullptr, *d_oflag = nullptr;
   // adjoint: per-face bed-offset parts [F][2] and, per cell, the list of its
   // entries in that array (CSR, face order)
   double* d_fdb = nullptr;
@@ -529,6 +544,7 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.cn = c->d_cn;
   a.res = c->d_res;
   a.flag = c->d_flag;
+  a.oflag = c->d_oflag;
   a.need = nullptr;
   a.wflag = nullptr;
   a.nwave = 0;
@@ -619,7 +635,14 @@ sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
 // then the general kernel on the cells it left (or on all cells)
 sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
                    int kind) {
-  const bool fast_ok = !c->p.tracer;
+  // a tracer replay runs the general kernel on every cell
+  const bool tracer = c->p.tracer != 0;
+  const bool fast_ok = !(tracer && c->rp[0] != nullptr);
+  if (fast_ok && tracer && fmode == F_FINAL) {
+    // the final kernel updates the degree flags; the tracer kernel reads the step's own
+    hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
+    HIPCHK(hipGetLastError());
+  }
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
     a.slot = slot;
@@ -633,6 +656,13 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
       a.nwave = L.nblk;
       const int cpb = L.wpb * kWave / L.P;
       HIPCHK(launch_elem(c->r, L.P, fmode, L.wpb, a, (L.ncell + cpb - 1) / cpb, c->s));
+    }
+    if (fast_ok && tracer) {
+      // tracer solve, C~ and tracer residual of the cells the fast kernel kept
+      sw_ctx::Scope sc(c, 5, 1);
+      StageArgs tr = a;
+      tr.need = c->d_need;
+      HIPCHK(launch_trc(c->r, L.P, fmode, tr, L.nblk, c->s));
     }
     StageArgs g = a;
     g.need = fast_ok ? c->d_need : nullptr;
@@ -974,6 +1004,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_cch_m0, M + 1);
     ALLOC(c->d_need, K);
     ALLOC(c->d_flag, K);
+    ALLOC(c->d_oflag, K);
     ALLOC(c->d_allwet, K);
     ALLOC(c->d_fdb, (size_t)2 * c->F);
     ALLOC(c->d_cfoff, (size_t)K + 1);
@@ -1736,13 +1767,13 @@ sw_status sw_get_workgroup(const sw_ctx* c, int32_t level, int32_t kernel, int32
 sw_status sw_profile(sw_ctx* c, int32_t on) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   c->prof = on != 0;
-  c->prof_mask = on > 1 ? (on >> 1) & 0x1F : 0x1F;
+  c->prof_mask = on > 1 ? (on >> 1) & 0x3F : 0x3F;
   return SW_OK;
 }
 
 sw_status sw_kernel_time(sw_ctx* c, int32_t kind, double* ms_total, int64_t* launches) {
   if (!c || !ms_total || !launches) return fail(SW_EINVAL, "NULL argument");
-  if (kind < 0 || kind > 4) return fail(SW_EINVAL, "kind must be 0..4");
+  if (kind < 0 || kind > 5) return fail(SW_EINVAL, "kind must be 0..5");
   for (auto& e : c->ev) {
     HIPCHK(hipEventSynchronize(e.b));
     float ms = 0.0f;

@@ -59,6 +59,7 @@ struct StageArgs {
                          //     general kernel reads: only flagged cells are processed)
   int8_t* wflag;         // [nwave] per wavefront of the level (64/P cells): 1 if a cell is flagged
   int nwave;
+  const int8_t* oflag;       // [K] degree flags of the step (the final kernel updates flag)
   const double* replay[3];   // tracer replay: recorded zeta, qx, qy of this stage (else NULL)
   double* rec_end[3];        // final combination: copy of the new zeta, qx, qy before any
                              // degree change of the next step (else NULL)
@@ -157,6 +158,7 @@ hipError_t launch_vjp_face(int r, const VjpFaceArgs& a, int nblk, hipStream_t s)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_stage_scan(int r, int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_elem(int r, int P, int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_trc(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_face(int r, int q, const FaceArgs& a, int nblk, hipStream_t s);
 
 // context hooks used by the ensemble driver

@@ -123,6 +123,11 @@ __global__ void k_fill8(int8_t* p, size_t n, int8_t v) {
   if (t < n) p[t] = v;
 }
 
+__global__ void k_copy8(const int8_t* a, int8_t* b, size_t n) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = a[t];
+}
+
 __global__ void k_copy(const double* a, double* b, size_t n) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) b[t] = a[t];

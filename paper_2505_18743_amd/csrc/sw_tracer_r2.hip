@@ -1,0 +1,10 @@
+// Fast tracer kernel instantiations for degree r = 2.
+#include "sw_tracer.inc"
+
+namespace swk {
+
+hipError_t launch_trc_r2(int P, int mode, const StageArgs& a, int nblk, hipStream_t s) {
+  return trc_r<2>(P, mode, a, nblk, s);
+}
+
+}  // namespace swk

@@ -369,3 +369,79 @@ def test_autotune_restores_the_state():
     a, r_ = ref.get_state(), tun.get_state()
     for f in range(3):
         assert rel(cpu(r_[f], o.m.K), cpu(a[f], o.m.K)) < TOL_STEP
+
+
+def test_full_size_tidal_quadtree_sampled_residuals():
+    """The 2-level quadtree with about 120k leaves (r=3, 32/16/8 samples per
+    level, tracer, tide on the west side), as built for the workload: the
+    residual of sampled cells (every level, cells at hanging faces and at the
+    tidal boundary) against the oracle on the 3x3 window of coarse cells around
+    each, with the library's own sample values."""
+    say("case: full-size tidal_quadtree_r3 sampled residuals")
+    from paper_2505_18743_amd import Solver
+    wl = workload("tidal_quadtree_r3")
+    d = wl["mesh"]
+    s = Solver(d, wl["params"], device="cuda:0")
+    xy = s.node_coords()
+    b = wl["bed"](xy[:, 0], xy[:, 1])
+    del xy
+    s.set_bathymetry(b)
+    s.set_manning(wl["manning"])
+    dof = s.dof_coords()
+    s.init_lake_at_rest(wl["eta0"](dof[:, 0], dof[:, 1]))
+    st = s.get_state()
+    L = d["nx0"] * d["dx0"]
+    x, y = dof[:, 0], dof[:, 1]
+    eta = st[0].cpu().numpy() + 0.4 * np.exp(-((x - 0.3 * L) ** 2 + (y - 0.6 * L) ** 2) / (0.1 * L) ** 2)
+    qx = 0.3 * np.sin(x / 3000.0) * np.cos(y / 2500.0)
+    qy = 0.2 * np.cos(x / 2000.0 + 0.5) * np.sin(y / 3500.0)
+    c = wl["tracer0"](x, y)
+    t = 3000.0
+    g = s.apply_operator(eta, qx, qy, c, t)
+    s.sync()
+    K, NP = s.n_cells, s.np_
+    res = [r_.cpu().numpy().reshape(K, NP) for r_ in g[:4]]
+    state = [np.asarray(v).reshape(K, NP) for v in (eta, qx, qy, c)]
+    scales = [max(np.abs(r_).max(), 1e-300) for r_ in res]
+    # context order: by level, then the description's order
+    member, local = s.cell_map()
+    lev, ci, cj = d["level"][local], d["i"][local], d["j"][local]
+    S = wl["params"]["S"]
+    nodes_per = np.array([S[l] ** 2 for l in lev])
+    noff = np.concatenate([[0], np.cumsum(nodes_per)])
+    key = {(int(lev[k]), int(ci[k]), int(cj[k])): k for k in range(K)}
+    coarse = np.stack([ci >> lev, cj >> lev], 1)
+    # picks: every level, cells next to a coarser or finer leaf, west boundary cells
+    rng = np.random.default_rng(17)
+    picks = []
+    for lv in range(3):
+        ks = np.nonzero(lev == lv)[0]
+        picks += list(rng.choice(ks, 6, replace=False))
+    hang = [k for k in rng.permutation(K)[:4000]
+            if any((int(lev[k]) - 1, int(ci[k] + di) >> 1, int(cj[k] + dj) >> 1) in key
+                   for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)))][:8]
+    west = [k for k in rng.permutation(K)[:20000] if ci[k] == 0][:4]
+    picks += hang + west
+    pkw = {k: v for k, v in wl["params"].items()}
+    params = Params(**{k: (tuple(v) if k in ("S", "tide") else v) for k, v in pkw.items()})
+    worst = 0.0
+    for k in picks:
+        cx, cy = coarse[k]
+        x0, x1 = max(cx - 1, 0), min(cx + 1, d["nx0"] - 1)
+        y0, y1 = max(cy - 1, 0), min(cy + 1, d["ny0"] - 1)
+        sel = np.nonzero((coarse[:, 0] >= x0) & (coarse[:, 0] <= x1) & (coarse[:, 1] >= y0) & (coarse[:, 1] <= y1))[0]
+        wlev = lev[sel]
+        m = Mesh(x1 - x0 + 1, y1 - y0 + 1, d["x0"] + x0 * d["dx0"], d["y0"] + y0 * d["dx0"], d["dx0"], wlev,
+                 ci[sel] - (x0 << wlev), cj[sel] - (y0 << wlev),
+                 ("elev" if x0 == 0 else "wall", "wall", "wall", "wall"))
+        o = Oracle(m, params)
+        o.set_bathymetry(np.concatenate([b[noff[q]:noff[q + 1]] for q in sel]))
+        o.set_manning(np.full(len(sel), 0.025))
+        F, Gx, Gy, R, _ = o.apply_operator([v[sel] for v in state], t)
+        w = int(np.nonzero(sel == k)[0][0])
+        for gg, rr, scale in zip(res, (F, Gx, Gy, R), scales):
+            worst = max(worst, np.abs(gg[k] - rr[w]).max() / scale)
+    say(f"  {len(picks)} sampled cells ({len(hang)} at hanging faces, {len(west)} on the tidal side), "
+        f"worst rel err {worst:.3e}")
+    assert len(hang) == 8 and len(west) == 4
+    assert worst < TOL_RHS
