@@ -192,7 +192,7 @@ def tableau(name: str):
     if name == "ssp3":                 # Table "SSP3" (Appendix A)
         A = [[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.25, 0.25, 0.0]]
         return A, [1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0], [0.0, 1.0, 0.5]
-    if name == "rk32":                 # explicit companion of the IMEX pair (Appendix A)
+    if name in ("rk32", "imex"):       # explicit companion of the IMEX pair (Appendix A)
         chi = 1.0 - math.sqrt(2.0) / 2.0
         a32 = 0.5
         A = [[0.0, 0.0, 0.0], [2.0 * chi, 0.0, 0.0], [1.0 - a32, a32, 0.0]]
@@ -203,6 +203,19 @@ def tableau(name: str):
         A = [[0.0] * 4, [0.5, 0, 0, 0], [0, 0.5, 0, 0], [0, 0, 1.0, 0]]
         return A, [1 / 6, 2 / 6, 2 / 6, 1 / 6], [0.0, 0.5, 0.5, 1.0]
     raise ValueError(f"unknown tableau {name!r}")
+
+
+def implicit_tableau(name: str):
+    """Implicit (DIRK) companion (A~, b~) of an IMEX pair: TR-BDF2 with
+    chi = 1 - sqrt(2)/2 for "imex" (Appendix A, right tableau), so that
+    b~ = b and c~ = c; None for the explicit schemes."""
+    if name != "imex":
+        return None
+    chi = 1.0 - math.sqrt(2.0) / 2.0
+    b2 = (1.0 - 2.0 * chi) / (4.0 * chi)
+    b = [1.0 - b2 - chi, b2, chi]
+    At = [[0.0, 0.0, 0.0], [chi, chi, 0.0], list(b)]
+    return At, b
 
 
 # ---------------------------------------------------------------------------
@@ -544,10 +557,11 @@ class Oracle:
                                           normal=NORMAL[side], kind=kind))
 
     # -- the spatial operator ---------------------------------------------
-    def residual(self, state, t, dbed=None, nman=None):
+    def residual(self, state, t, dbed=None, nman=None, friction=True):
         """Weak residuals F (eq:mass_rhs), G = (Gx, Gy) (eq:discharge_rhs plus the
-        explicit friction L of eq:discharge_rhs_implicit) and R (eq:r_concentration),
-        for every degree-r test function, before any mass solve.
+        explicit friction L of eq:discharge_rhs_implicit; without it when
+        friction=False) and R (eq:r_concentration), for every degree-r test
+        function, before any mass solve.
 
         Also returns the positivity time-step bound min over face nodes and
         face sides of w * J_K / (lambda l_Gamma) (Prop. 3.2, eq:deltat_fe),
@@ -580,10 +594,11 @@ class Oracle:
             # F_i += int q . grad psi_i
             F = F.index_add(0, idx, (W * qxq) @ Bx + (W * qyq) @ By)
             # G_i,k += int q_k (u . grad psi_i) - g h d_k zeta psi_i - gamma q_k psi_i
+            fr = 1.0 if friction else 0.0
             Gx = Gx.index_add(0, idx, (W * qxq * ux) @ Bx + (W * qxq * uy) @ By
-                              - (W * g * h * zx) @ Bv - (W * gam * qxq) @ Bv)
+                              - (W * g * h * zx) @ Bv - fr * ((W * gam * qxq) @ Bv))
             Gy = Gy.index_add(0, idx, (W * qyq * ux) @ Bx + (W * qyq * uy) @ By
-                              - (W * g * h * zy) @ Bv - (W * gam * qyq) @ Bv)
+                              - (W * g * h * zy) @ Bv - fr * ((W * gam * qyq) @ Bv))
             if p.tracer:
                 R = R.index_add(0, idx, (W * cq * qxq) @ Bx + (W * cq * qyq) @ By)
         dtb = torch.tensor(float("inf"), dtype=DT)
@@ -810,6 +825,7 @@ class Oracle:
         eq:algebraic_discharge, eq:algebraic_concentration)."""
         p = self.p
         A, b, cc = tableau(p.rk)
+        imp = implicit_tableau(p.rk)     # IMEX: friction with the DIRK companion
         s = len(b)
         zeta, qx, qy, c = [x.clone() for x in self.state]
         r = p.r
@@ -860,6 +876,7 @@ class Oracle:
         Qyn = torch.einsum("kij,kj->ki", Mq, qy)
         state_n = [zeta, qx, qy, c]
         res = []
+        lres = []                        # IMEX: implicit-part residuals L of each stage
         cur = state_n
         t0 = self.t
         for l in range(s + 1):
@@ -878,6 +895,15 @@ class Oracle:
                 T = Hn + dt * acc[0]
                 QX = Qxn + dt * acc[1]
                 QY = Qyn + dt * acc[2]
+                if imp is not None:
+                    # eq:algebraic_discharge: + dt sum_m a~_lm L^(m)
+                    coeft = imp[0][l] if l < s else imp[1]
+                    accL = [torch.zeros_like(Hn), torch.zeros_like(Hn)]
+                    for m_ in range(upto):
+                        if coeft[m_] != 0.0:
+                            accL = [accL[0] + coeft[m_] * lres[m_][0], accL[1] + coeft[m_] * lres[m_][1]]
+                    QX = QX + dt * accL[0]
+                    QY = QY + dt * accL[1]
                 CT = Cn + dt * acc[3]
                 Tbar = T.sum(1)
                 diag["min_target"] = min(diag["min_target"], float(Tbar.min()) if K else 0.0)
@@ -896,16 +922,27 @@ class Oracle:
                         nc[idx] = self._tracer_solve(lv, h, CT[idx], c[idx], full)
                     else:
                         nc[idx] = c[idx]
-                # discharge (eq:algebraic_discharge with A = exact mass matrix)
-                qxf = torch.linalg.solve(Mq, QX.unsqueeze(-1)).squeeze(-1)
-                qyf = torch.linalg.solve(Mq, QY.unsqueeze(-1)).squeeze(-1)
-                qx0 = (QX.sum(1) / Jac)[:, None].expand_as(qxf)
-                qy0 = (QY.sum(1) / Jac)[:, None].expand_as(qyf)
+                # discharge (eq:algebraic_discharge with A = exact mass matrix; for
+                # an IMEX stage A^(l) = M + a~_ll dt Gam(q^(l-1), h^(l-1)),
+                # eq:mass_matrix_discharge, the previous stage's friction)
+                Amat, Asum = Mq, Jac
+                if imp is not None and l < s and imp[0][l][l] != 0.0:
+                    _, _, Gam = self._friction(cur)
+                    Amat = Mq + (imp[0][l][l] * dt) * Gam
+                    Asum = Jac + (imp[0][l][l] * dt) * Gam.sum((1, 2))
+                qxf = torch.linalg.solve(Amat, QX.unsqueeze(-1)).squeeze(-1)
+                qyf = torch.linalg.solve(Amat, QY.unsqueeze(-1)).squeeze(-1)
+                qx0 = (QX.sum(1) / Asum)[:, None].expand_as(qxf)
+                qy0 = (QY.sum(1) / Asum)[:, None].expand_as(qyf)
                 nqx = torch.where(full_all[:, None], qxf, qx0)
                 nqy = torch.where(full_all[:, None], qyf, qy0)
                 cur = [nz, nqx, nqy, nc]
             if l < s:
-                F, Gx, Gy, R, dtb = self.residual(cur, t0 + cc[l] * (dt if dt is not None else 0.0))
+                F, Gx, Gy, R, dtb = self.residual(cur, t0 + cc[l] * (dt if dt is not None else 0.0),
+                                                  friction=imp is None)
+                if imp is not None:
+                    Lx, Ly, _ = self._friction(cur)
+                    lres.append((Lx, Ly))
                 if l == 0 and dt is None:
                     dt = p.cfl * float(dtb)
                     if l == 0 and cc[0] != 0.0:
@@ -919,6 +956,34 @@ class Oracle:
             mass += float((lv.W * h).sum())
         diag.update(dt=dt, mass=mass, n_r0=int((self.flag == 0).sum()))
         return diag
+
+    def _friction(self, state, nman=None):
+        """Implicit-part terms of the discharge equation at a state:
+        L_i = -int gamma q psi_i (eq:discharge_rhs_implicit) and the matrix
+        Gam_ij = int gamma psi_i psi_j of eq:mass_matrix_discharge, with
+        gamma = g n^2 |q| / h_des^(7/3) at the sample nodes (eq:manning with the
+        desingularised depth of eq:velocity, as L uses)."""
+        p = self.p
+        zeta, qx, qy = state[0], state[1], state[2]
+        nman = self.nman if nman is None else nman
+        K = self.m.K
+        Lx = torch.zeros(K, self.np_, dtype=DT)
+        Ly = torch.zeros(K, self.np_, dtype=DT)
+        Gam = torch.zeros(K, self.np_, self.np_, dtype=DT)
+        for lv in self.levels:
+            idx = lv.idx
+            if len(idx) == 0:
+                continue
+            zq = zeta[idx] @ lv.Bv.T
+            qxq, qyq = qx[idx] @ lv.Bv.T, qy[idx] @ lv.Bv.T
+            h = _pos(zq + self.zb_eff(lv, None))
+            ih = _inv_des(h, p.eps)
+            gam = p.g * nman[idx][:, None] ** 2 * _safe_norm(qxq, qyq) * ih ** (7.0 / 3.0)
+            W, Bv = lv.W, lv.Bv
+            Lx[idx] = -((W * gam * qxq) @ Bv)
+            Ly[idx] = -((W * gam * qyq) @ Bv)
+            Gam[idx] = torch.einsum("kq,qi,qj->kij", W * gam, Bv, Bv)
+        return Lx, Ly, Gam
 
     def apply_operator(self, state=None, t=None):
         st = self.state if state is None else [torch.as_tensor(np.asarray(s, dtype=np.float64)).reshape(self.m.K, self.np_) for s in state]
