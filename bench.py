@@ -18,6 +18,8 @@ per-kernel events.  Besides the metric the line carries
                 (about 120k leaves, r = 3): DoF-updates/s of its coupled step;
   ensemble:     ensemble_64, batched + graph-replayed vs one by one;
   adjoint:      adjoint_128 gradient, backward vs forward time;
+  imex:         the same beach case stepped with the IMEX pair (friction by
+                the TR-BDF2 companion) and with plain RK32, DoF-updates/s;
   cpu_baseline: the oracle timed on the host cores on a bounded window of
                 the same workload.
 """
@@ -280,6 +282,49 @@ def adjoint_bench(device, reps=3):
                 adjoint_over_forward=b / f, adjoint_over_plain_forward=b / p, loss=float(loss.detach()))
 
 
+def imex_bench(steps, warmup, device):
+    """The 256x256 beach dam break (Manning 0.025) stepped with the IMEX pair
+    (RK32 explicit, TR-BDF2 for the friction) and, for reference, with the
+    explicit RK32 scheme: DoF-updates/s per stage of each and the IMEX step's
+    kernel-class shares."""
+    import torch
+    from workloads import workload
+    out = {}
+    for rk in ("imex", "rk32"):
+        wl = workload("beach_dambreak_256")
+        wl["params"] = dict(wl["params"], rk=rk)
+        s, reset, _ = setup(wl, device)
+        dofs_stage = 3 * (int(wl["params"]["r"]) + 1) ** 2 * s.n_cells
+        s.run(warmup)
+        s.sync()
+        reset()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        s.run(steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        diag = s.diagnostics()
+        out[rk] = dict(ms_per_step=ms / steps, value=dofs_stage * 3 * steps / (ms * 1e-3),
+                       max_newton_it=diag["max_newton_it"], r0_cells=diag["n_r0_cells"])
+        if rk == "imex":
+            reset()
+            torch.cuda.synchronize()
+            s.profile(True)
+            s.kernel_time_reset()
+            ev0.record()
+            s.run(steps)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms2 = ev0.elapsed_time(ev1)
+            out[rk]["kernel_share"] = {k: round(v[0] / ms2, 4) for k, v in s.kernel_times().items()}
+            s.profile(False)
+        s.close()
+    return dict(workload="beach_dambreak_256", steps=steps, unit="DoF-updates/s", **out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +338,8 @@ def main():
     ap.add_argument("--qt-steps", type=int, default=100, help="tidal_quadtree_r3 steps (0: skip)")
     ap.add_argument("--elem-wpb", type=int, default=0, help="wavefronts per workgroup of the fast element kernel "
                     "(0: library default)")
-    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree"], default=None,
+    ap.add_argument("--imex-steps", type=int, default=100, help="beach steps of the IMEX leg (0: skip)")
+    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex"], default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
@@ -317,6 +363,9 @@ def main():
         return
     if args.only == "quadtree":
         print(json.dumps(quadtree_bench(args.qt_steps, 3, dev)), flush=True)
+        return
+    if args.only == "imex":
+        print(json.dumps(imex_bench(args.imex_steps, 3, dev)), flush=True)
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
@@ -422,6 +471,8 @@ def main():
         line["ensemble"] = ensemble_bench(args.ens_steps, 3, dev)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_bench(dev)
+    if args.imex_steps > 0:
+        line["imex"] = imex_bench(args.imex_steps, 3, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     else:

@@ -70,7 +70,16 @@ enum { SW_BC_WALL = 0,      /* ghost mirrors the normal discharge               
 enum { SW_RULE_EQ = 0,      /* closed equispaced (composite trapezoid) rule         */
        SW_RULE_GLL = 1 };   /* Gauss-Legendre-Lobatto rule                         */
 
-enum { SW_RK_FE = 0, SW_RK_SSP3 = 1, SW_RK_RK32 = 2, SW_RK_RK44 = 3 };  /* Appendix A */
+enum { SW_RK_FE = 0, SW_RK_SSP3 = 1, SW_RK_RK32 = 2, SW_RK_RK44 = 3,  /* Appendix A */
+       SW_RK_IMEX = 4 };    /* Sec. 3.1 IMEX pair of Appendix A: the explicit     */
+                            /* RK32 tableau for everything but the Manning        */
+                            /* friction, TR-BDF2 (chi = 1 - sqrt(2)/2, b~ = b)    */
+                            /* for the friction.  A stage solves                  */
+                            /* (M + a~_ll dt Gam) q = M q^n + dt (sum a G +       */
+                            /* sum a~ L) (eq:algebraic_discharge,                 */
+                            /* eq:mass_matrix_discharge) with Gam linearised at   */
+                            /* the previous stage; the final combination is       */
+                            /* explicit.  sw_vjp_step rejects such a context.     */
 
 typedef struct {
   int32_t nx0, ny0;          /* coarse grid, cells of size dx0                     */

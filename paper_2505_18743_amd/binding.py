@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libswdg.so")
 
 BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3, "state": 4, "discharge": 5}
 RULE = {"eq": 0, "gll": 1}
-RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3}
+RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3, "imex": 4}
 
 EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_cell_map", "sw_counts",
            "sw_node_coords", "sw_dof_coords", "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset",
@@ -407,7 +407,7 @@ class Solver:
         return outs[0], outs[1], outs[2], pb[0], pb[1]
 
     def n_stages(self):
-        return {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[self.params.get("rk", "ssp3")]
+        return {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4, "imex": 3}[self.params.get("rk", "ssp3")]
 
     def _flow_buf(self, x, n, what):
         if (not torch.is_tensor(x) or x.numel() != n * 3 * self.n_dofs or not x.is_contiguous()

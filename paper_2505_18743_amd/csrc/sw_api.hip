@@ -277,6 +277,9 @@ struct sw_ctx {
   std::vector<double> cdx;
   std::vector<LevelH> lv;
   double A[4][4]{}, b[4]{}, c[4]{};
+  double At[4][4]{};          // implicit companion (IMEX), zero otherwise
+  bool imex = false;
+  double* d_lres = nullptr;   // IMEX: implicit-part residuals [slot][2][K][NP]
   int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr, *d_cmem = nullptr;
   double *d_zb = nullptr, *d_braw = nullptr, *d_db = nullptr, *d_bvec = nullptr, *d_zmax = nullptr;
   double *d_nman = nullptr, *d_cdx = nullptr, *d_cw1 = nullptr, *d_zf = nullptr;
@@ -387,7 +390,7 @@ void tableau(int rk, int& s, double A[4][4], double b[4], double c[4]) {
     b[2] = 2.0 / 3.0;
     c[1] = 1.0;
     c[2] = 0.5;
-  } else if (rk == SW_RK_RK32) {
+  } else if (rk == SW_RK_RK32 || rk == SW_RK_IMEX) {
     s = 3;
     const double chi = 1.0 - std::sqrt(2.0) / 2.0, a32 = 0.5;
     A[1][0] = 2.0 * chi;
@@ -412,6 +415,20 @@ void tableau(int rk, int& s, double A[4][4], double b[4], double c[4]) {
     c[2] = 0.5;
     c[3] = 1.0;
   }
+}
+
+// implicit (DIRK) companion of the IMEX pair: TR-BDF2, chi = 1 - sqrt(2)/2,
+// b~ = b (Appendix A); zero for the explicit schemes
+void implicit_tableau(int rk, double At[4][4]) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) At[i][j] = 0.0;
+  if (rk != SW_RK_IMEX) return;
+  const double chi = 1.0 - std::sqrt(2.0) / 2.0, b2 = (1.0 - 2.0 * chi) / (4.0 * chi);
+  At[1][0] = chi;
+  At[1][1] = chi;
+  At[2][0] = 1.0 - b2 - chi;
+  At[2][1] = b2;
+  At[2][2] = chi;
 }
 
 int64_t key(int L, int i, int j) { return ((int64_t)L << 52) | ((int64_t)i << 26) | (int64_t)j; }
@@ -449,7 +466,8 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   std::vector<double> tab;
   const size_t o_w = 0, o_l = o_w + S, o_d = o_l + (size_t)S * N1, o_m0 = o_d + (size_t)S * N1,
                o_mq = o_m0 + (size_t)NP * NP, o_mean = o_mq + (size_t)NP * NP, o_fl = o_mean + NP,
-               o_wl = o_fl + (size_t)3 * S * N1, o_wd = o_wl + (size_t)S * N1, total = o_wd + (size_t)S * N1;
+               o_wl = o_fl + (size_t)3 * S * N1, o_wd = o_wl + (size_t)S * N1, o_mqf = o_wd + (size_t)S * N1,
+               total = o_mqf + (size_t)NP * NP;
   tab.assign(total, 0.0);
   for (int a = 0; a < S; ++a) {
     tab[o_w + a] = L.wh[a];
@@ -493,6 +511,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
       for (int a = 0; a < N1; ++a) s += wg[a] * wg[b] * lag(xi, j % N1, xg[a]) * lag(xi, j / N1, xg[b]);
     mean[j] = s;
   }
+  for (int i = 0; i < NP * NP; ++i) tab[o_mqf + i] = Mq[i];
   if (!spd_inverse(M0, NP) || !spd_inverse(Mq, NP)) return fail(SW_EINVAL, "reference mass matrix not SPD");
   for (int i = 0; i < NP * NP; ++i) {
     tab[o_m0 + i] = M0[i];
@@ -511,6 +530,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.fl = L.d_tab + o_fl;
   L.tabs.wl = L.d_tab + o_wl;
   L.tabs.wd = L.d_tab + o_wd;
+  L.tabs.mq = L.d_tab + o_mqf;
   L.tabs.S = S;
   L.w1 = L.wh[0];
   return SW_OK;
@@ -566,6 +586,11 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.tracer = c->p.tracer ? 1 : 0;
   a.fric = 1;
   a.adapt = c->p.adapt_degree ? 1 : 0;
+  a.imex = c->imex ? 1 : 0;
+  a.lres = c->d_lres;
+  for (int f = 0; f < 3; ++f) a.uprev[f] = nullptr;
+  for (int m = 0; m < 4; ++m) a.at[m] = 0.0;
+  a.att = 0.0;
   return a;
 }
 
@@ -633,11 +658,13 @@ sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
 
 // element work of one phase on every level: the fast kernel where it applies,
 // then the general kernel on the cells it left (or on all cells)
+// IMEX: coeft are the implicit weights of the combination, att its diagonal
+// weight and uprev the previous stage's state (the friction matrix's point)
 sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
-                   int kind) {
-  // a tracer replay runs the general kernel on every cell
+                   int kind, const double* coeft = nullptr, double att = 0.0, double* const* uprev = nullptr) {
+  // a tracer replay and the IMEX scheme run the general kernel on every cell
   const bool tracer = c->p.tracer != 0;
-  const bool fast_ok = !(tracer && c->rp[0] != nullptr);
+  const bool fast_ok = !(tracer && c->rp[0] != nullptr) && !c->imex;
   if (fast_ok && tracer && fmode == F_FINAL) {
     // the final kernel updates the degree flags; the tracer kernel reads the step's own
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
@@ -648,6 +675,9 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
     a.slot = slot;
     a.nterm = nterm;
     for (int m = 0; m < 4; ++m) a.a[m] = coef ? coef[m] : 0.0;
+    for (int m = 0; m < 4; ++m) a.at[m] = coeft ? coeft[m] : 0.0;
+    a.att = att;
+    for (int f = 0; f < 3; ++f) a.uprev[f] = uprev ? uprev[f] : nullptr;
     a.diag_init = diag_init;
     if (fast_ok) {
       sw_ctx::Scope sc(c, kind, 1);
@@ -747,7 +777,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   const sw_params* p = &params[0];
   if (p->r < 1 || p->r > 3) return fail(SW_EINVAL, "r must be 1, 2 or 3");
   if (p->rule != SW_RULE_EQ && p->rule != SW_RULE_GLL) return fail(SW_EINVAL, "unknown rule");
-  if (p->rk < SW_RK_FE || p->rk > SW_RK_RK44) return fail(SW_EINVAL, "unknown RK scheme");
+  if (p->rk < SW_RK_FE || p->rk > SW_RK_IMEX) return fail(SW_EINVAL, "unknown RK scheme");
   if (!(p->eps > 0.0)) return fail(SW_EINVAL, "eps must be > 0");
   if (p->newton_max < 1 || p->newton_max > 1000) return fail(SW_EINVAL, "newton_max out of range");
   if (p->n_levels < 1 || p->n_levels > 8) return fail(SW_EINVAL, "n_levels must be 1..8");
@@ -791,6 +821,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   c->N1 = p->r + 1;
   c->NP = c->N1 * c->N1;
   tableau(p->rk, c->ns, c->A, c->b, c->c);
+  implicit_tableau(p->rk, c->At);
+  c->imex = p->rk == SW_RK_IMEX;
   const int M = n_members;
   // per-member validation: level order, extent, tiling, duplicates
   int maxL = 0;
@@ -1010,6 +1042,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_cfoff, (size_t)K + 1);
     ALLOC(c->d_cfent, (size_t)2 * c->F);
     ALLOC(c->d_gof, c->F);
+    if (c->imex) ALLOC(c->d_lres, (size_t)kNSlot * 2 * KN);
 #undef ALLOC
   }
   for (auto& L : c->lv) {
@@ -1346,6 +1379,7 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
   HIPCHK(hipGetLastError());
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
+    a.imex = 0;   // the whole residual, friction included
     a.in[0] = eta;
     a.in[1] = qx;
     a.in[2] = qy;
@@ -1401,9 +1435,15 @@ sw_status sw_rk_stage(sw_ctx* c, int32_t l) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (l < 2 || l > c->ns) return fail(SW_EINVAL, "stage index out of range");
   if (c->stage_done != l - 1) return fail(SW_EINVAL, "stages must be taken in order after sw_step_begin");
-  double coef[4];
-  for (int m = 0; m < 4; ++m) coef[m] = m < l - 1 ? c->A[l - 1][m] : 0.0;
-  sw_status st = elements(c, F_STAGE, M_STAGE, -1, l - 1, l - 1, coef, l == 2 ? 1 : 0, 1);
+  double coef[4], coeft[4];
+  for (int m = 0; m < 4; ++m) {
+    coef[m] = m < l - 1 ? c->A[l - 1][m] : 0.0;
+    coeft[m] = m < l - 1 ? c->At[l - 1][m] : 0.0;
+  }
+  // IMEX: the friction matrix at the previous stage (stage 1 is u^n)
+  double* const* uprev = (l == 2) ? c->d_sn : c->d_ss;
+  sw_status st = elements(c, F_STAGE, M_STAGE, -1, l - 1, l - 1, coef, l == 2 ? 1 : 0, 1, coeft,
+                          c->At[l - 1][l - 1], uprev);
   if (st != SW_OK) return st;
   const double* sts[4] = {c->d_ss[0], c->d_ss[1], c->d_ss[2], c->d_ss[3]};
   if ((st = faces(c, sts, c->c[l - 1], l - 1)) != SW_OK) return st;
@@ -1415,7 +1455,8 @@ sw_status sw_step_end(sw_ctx* c) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (c->stage_done != c->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
   // final combination; the same pass prepares the next step's start (slot 0)
-  sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2);
+  // (IMEX: explicit, the implicit weights b~ = b)
+  sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2, c->b);
   if (st != SW_OK) return st;
   // per-member diagnostics (two-level segmented reduction); advances each member's time
   hipLaunchKernelGGL(k_diag_part_seg, dim3(c->ncch), dim3(256), 0, c->s, c->d_cdiag, c->d_flag, c->d_cch,
@@ -1590,6 +1631,7 @@ sw_status sw_vjp_step(sw_ctx* c, const double* stages, double t, double dt, doub
   if (!stages || !state_bar || !n_bar || !db_bar) return fail(SW_EINVAL, "arrays of sw_vjp_step must be non-NULL");
   if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_vjp_step needs the step's fixed dt > 0");
   if (c->p.tracer) return fail(SW_EINVAL, "the step adjoint covers runs without a tracer");
+  if (c->imex) return fail(SW_EINVAL, "the step adjoint covers the explicit schemes, not IMEX");
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_vjp_step cannot run inside an open step");
   sw_status st = need_inputs(c);
   if (st != SW_OK) return st;

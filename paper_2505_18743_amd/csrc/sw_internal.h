@@ -27,6 +27,7 @@ struct LevelTabs {
   const double* d;      // [S][N1]      l_k'(xhat_a)
   const double* m0inv;  // [NP][NP]     inverse all-wet rule mass matrix, unit square
   const double* mqinv;  // [NP][NP]     inverse exact mass matrix, unit square
+  const double* mq;     // [NP][NP]     exact mass matrix, unit square
   const double* meanw;  // [NP]         int psi_j over the unit square
   const double* fl;     // [3][S][N1]   l_k at face nodes: s, s/2, (1+s)/2
   const double* wl;     // [S][N1]      w_a l_k(xhat_a)
@@ -60,6 +61,14 @@ struct StageArgs {
   int8_t* wflag;         // [nwave] per wavefront of the level (64/P cells): 1 if a cell is flagged
   int nwave;
   const int8_t* oflag;       // [K] degree flags of the step (the final kernel updates flag)
+  // IMEX (friction with the implicit companion): implicit-part residuals L of
+  // each stage [slot][2][K][NP], the previous stage's state (friction matrix),
+  // the implicit weights of the combination and its diagonal weight
+  int imex;
+  double* lres;
+  const double* uprev[3];
+  double at[4];
+  double att;
   const double* replay[3];   // tracer replay: recorded zeta, qx, qy of this stage (else NULL)
   double* rec_end[3];        // final combination: copy of the new zeta, qx, qy before any
                              // degree change of the next step (else NULL)
