@@ -130,3 +130,56 @@ def test_imex_staged_calls_and_adjoint_rejection():
         s1.vjp_step(stages, 0.0, 10.0, z(3 * s1.n_dofs), z(s1.n_cells), z(s1.n_cells))
     s1.close()
     s2.close()
+
+
+def test_imex_channel_parity():
+    say("case: strong-friction channel (n = 1), N = 10, r = 1, IMEX at dt = 0.04 s (RK32 diverges at 0.02), 100 steps")
+    from channel import channel_oracle, inflow
+    o, b = channel_oracle(10, 1, "imex")
+    s = gpu_from_oracle(o, b)
+    s.set_boundary_state(inflow)
+    s.set_state(*o.get_state())
+    for _ in range(100):
+        o.step(0.04)
+        s.step(0.04)
+    s.sync()
+    got = [cpu(x, o.m.K) for x in s.get_state()[:3]]
+    ref = o.get_state()
+    qs = max(np.abs(ref[1]).max(), np.abs(ref[2]).max())
+    errs = (rel(got[0], ref[0]), np.abs(got[1] - ref[1]).max() / qs, np.abs(got[2] - ref[2]).max() / qs)
+    for name, e in zip(("zeta", "qx", "qy"), errs):
+        say(f"  {name} rel err {e:.3e}")
+        assert e < TOL_STEP
+    s.close()
+
+
+@pytest.mark.parametrize("r,Ns,rate", [(1, (20, 40), 1.6), (2, (10, 20), 1.8)])
+def test_imex_channel_steady_state_converges(r, Ns, rate):
+    """Sec. 4.3: the IMEX run from rest settles on a steady state whose surface
+    converges to the ODE profile of eq:const_discharge as the mesh is refined
+    (the paper's convergence study; 600 s of flow)."""
+    from channel import channel_oracle, inflow, steady_profile
+    xe, ze = steady_profile()
+    errs = []
+    for N in Ns:
+        dt = 0.4 / N / r
+        o, b = channel_oracle(N, r, "imex")
+        s = gpu_from_oracle(o, b)
+        s.set_boundary_state(inflow)
+        s.set_state(*o.get_state())
+        nst = int(round(600.0 / dt))
+        s.run(nst - 1, dt)
+        s.sync()
+        z_prev = cpu(s.get_state()[0], N).copy()
+        s.step(dt)
+        s.sync()
+        z = cpu(s.get_state()[0], N)
+        d = o.dof_coords()
+        e = float(np.sqrt(np.mean((z - np.interp(d[..., 0], xe, ze)) ** 2)))
+        say(f"  r={r} N={N} dt={dt:.4f}: rms zeta error {e:.3e}, last-step change {np.abs(z - z_prev).max():.1e}")
+        assert np.abs(z - z_prev).max() < 1e-8
+        errs.append(e)
+        s.close()
+    got = np.log2(errs[0] / errs[1])
+    say(f"  rate {got:.2f}")
+    assert got > rate and errs[1] < 0.02

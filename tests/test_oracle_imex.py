@@ -111,3 +111,40 @@ def test_imex_mass_conservation_wet_dry():
     for _ in range(15):
         o.step()
     assert o.total_mass() == pytest.approx(m0, rel=1e-13)
+
+
+def test_channel_ode_reference_pins():
+    """The steady-flow ODE solution of the strong-friction channel: RK4 at two
+    resolutions agrees to 1e-9; zeta = 0 at the outflow; the surface rises
+    upstream (friction slope); the flow stays subcritical."""
+    from channel import G, Q0, depth, steady_profile
+    x1, z1 = steady_profile(4000)
+    x2, z2 = steady_profile(20000)
+    assert abs(z2[-1]) < 1e-14
+    assert np.abs(np.interp(x1, x2, z2) - z1).max() < 1e-9
+    assert np.all(np.diff(z2) < 0.0)
+    h = z2 + depth(x2)
+    assert (Q0 ** 2 / (G * h ** 3)).max() < 0.05
+
+
+def test_imex_channel_runs_beyond_the_explicit_limit():
+    """Sec. 4.3, strong friction on the coarsest mesh (N = 10, r = 1): from
+    rest, RK32 diverges at dt = 0.02 s, while IMEX runs stably at 2.5 times
+    that step (the factor the paper reports) and stays near the steady
+    profile; RK32 at dt = 0.01 s is still stable over the same start."""
+    from channel import channel_oracle, steady_profile
+    def run(rk, dt, n):
+        o, _ = channel_oracle(10, 1, rk)
+        with np.errstate(all="ignore"):
+            for _ in range(n):
+                o.step(dt)
+                z = o.get_state()[0]
+                if not np.all(np.isfinite(z)) or np.abs(z).max() > 1e3:
+                    return None
+        return o.get_state()[0]
+    assert run("rk32", 0.02, 50) is None
+    assert run("rk32", 0.01, 150) is not None
+    z = run("imex", 0.05, 400)
+    assert z is not None
+    xe, ze = steady_profile(4000)
+    assert z.max() < 1.05 * ze.max() and z.min() > -0.5
