@@ -280,6 +280,7 @@ struct sw_ctx {
   double At[4][4]{};          // implicit companion (IMEX), zero otherwise
   bool imex = false;
   double* d_lres = nullptr;   // IMEX: implicit-part residuals [slot][2][K][NP]
+  double* d_gam = nullptr;    // IMEX: friction matrix of the last volume pass [K][NP(NP+1)/2]
   int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr, *d_cmem = nullptr;
   double *d_zb = nullptr, *d_braw = nullptr, *d_db = nullptr, *d_bvec = nullptr, *d_zmax = nullptr;
   double *d_nman = nullptr, *d_cdx = nullptr, *d_cw1 = nullptr, *d_zf = nullptr;
@@ -588,7 +589,7 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.adapt = c->p.adapt_degree ? 1 : 0;
   a.imex = c->imex ? 1 : 0;
   a.lres = c->d_lres;
-  for (int f = 0; f < 3; ++f) a.uprev[f] = nullptr;
+  a.gam = c->d_gam;
   for (int m = 0; m < 4; ++m) a.at[m] = 0.0;
   a.att = 0.0;
   return a;
@@ -658,13 +659,13 @@ sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
 
 // element work of one phase on every level: the fast kernel where it applies,
 // then the general kernel on the cells it left (or on all cells)
-// IMEX: coeft are the implicit weights of the combination, att its diagonal
-// weight and uprev the previous stage's state (the friction matrix's point)
+// IMEX: coeft are the implicit weights of the combination and att its
+// diagonal weight
 sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
-                   int kind, const double* coeft = nullptr, double att = 0.0, double* const* uprev = nullptr) {
-  // a tracer replay and the IMEX scheme run the general kernel on every cell
+                   int kind, const double* coeft = nullptr, double att = 0.0) {
+  // a tracer replay runs the general kernel on every cell
   const bool tracer = c->p.tracer != 0;
-  const bool fast_ok = !(tracer && c->rp[0] != nullptr) && !c->imex;
+  const bool fast_ok = !(tracer && c->rp[0] != nullptr);
   if (fast_ok && tracer && fmode == F_FINAL) {
     // the final kernel updates the degree flags; the tracer kernel reads the step's own
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
@@ -677,15 +678,15 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
     for (int m = 0; m < 4; ++m) a.a[m] = coef ? coef[m] : 0.0;
     for (int m = 0; m < 4; ++m) a.at[m] = coeft ? coeft[m] : 0.0;
     a.att = att;
-    for (int f = 0; f < 3; ++f) a.uprev[f] = uprev ? uprev[f] : nullptr;
     a.diag_init = diag_init;
     if (fast_ok) {
       sw_ctx::Scope sc(c, kind, 1);
       a.need = c->d_need;
       a.wflag = L.d_wflag;
       a.nwave = L.nblk;
-      const int cpb = L.wpb * kWave / L.P;
-      HIPCHK(launch_elem(c->r, L.P, fmode, L.wpb, a, (L.ncell + cpb - 1) / cpb, c->s));
+      const int wpb = c->imex ? 1 : L.wpb;   // the IMEX variant runs one wavefront per workgroup
+      const int cpb = wpb * kWave / L.P;
+      HIPCHK(launch_elem(c->r, L.P, fmode, wpb, a, (L.ncell + cpb - 1) / cpb, c->s));
     }
     if (fast_ok && tracer) {
       // tracer solve, C~ and tracer residual of the cells the fast kernel kept
@@ -1042,7 +1043,10 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_cfoff, (size_t)K + 1);
     ALLOC(c->d_cfent, (size_t)2 * c->F);
     ALLOC(c->d_gof, c->F);
-    if (c->imex) ALLOC(c->d_lres, (size_t)kNSlot * 2 * KN);
+    if (c->imex) {
+      ALLOC(c->d_lres, (size_t)kNSlot * 2 * KN);
+      ALLOC(c->d_gam, (size_t)K * (c->NP * (c->NP + 1) / 2));
+    }
 #undef ALLOC
   }
   for (auto& L : c->lv) {
@@ -1440,10 +1444,9 @@ sw_status sw_rk_stage(sw_ctx* c, int32_t l) {
     coef[m] = m < l - 1 ? c->A[l - 1][m] : 0.0;
     coeft[m] = m < l - 1 ? c->At[l - 1][m] : 0.0;
   }
-  // IMEX: the friction matrix at the previous stage (stage 1 is u^n)
-  double* const* uprev = (l == 2) ? c->d_sn : c->d_ss;
+  // (IMEX: the friction matrix of the previous stage is the one its volume pass stored)
   sw_status st = elements(c, F_STAGE, M_STAGE, -1, l - 1, l - 1, coef, l == 2 ? 1 : 0, 1, coeft,
-                          c->At[l - 1][l - 1], uprev);
+                          c->At[l - 1][l - 1]);
   if (st != SW_OK) return st;
   const double* sts[4] = {c->d_ss[0], c->d_ss[1], c->d_ss[2], c->d_ss[3]};
   if ((st = faces(c, sts, c->c[l - 1], l - 1)) != SW_OK) return st;

@@ -62,11 +62,13 @@ struct StageArgs {
   int nwave;
   const int8_t* oflag;       // [K] degree flags of the step (the final kernel updates flag)
   // IMEX (friction with the implicit companion): implicit-part residuals L of
-  // each stage [slot][2][K][NP], the previous stage's state (friction matrix),
+  // each stage [slot][2][K][NP]; the friction matrix Gam_ij = int gamma psi_i
+  // psi_j at the state of the last volume pass [K][NP(NP+1)/2] (packed lower
+  // triangle; written by every volume pass, read by the next stage's solve);
   // the implicit weights of the combination and its diagonal weight
   int imex;
   double* lres;
-  const double* uprev[3];
+  double* gam;
   double at[4];
   double att;
   const double* replay[3];   // tracer replay: recorded zeta, qx, qy of this stage (else NULL)

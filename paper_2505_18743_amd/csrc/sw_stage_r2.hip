@@ -16,12 +16,12 @@ static hipError_t stage_p(int mode, const StageArgs& a, int nblk, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int P, int WPB>
+template <int P, int WPB, int IMEX = 0>
 static hipError_t elem_pw(int mode, const StageArgs& a, int nblk, hipStream_t s) {
   switch (mode) {
-    case F_START: hipLaunchKernelGGL((k_elem<2, P, F_START, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
-    case F_STAGE: hipLaunchKernelGGL((k_elem<2, P, F_STAGE, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
-    case F_FINAL: hipLaunchKernelGGL((k_elem<2, P, F_FINAL, WPB>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
+    case F_START: hipLaunchKernelGGL((k_elem<2, P, F_START, WPB, IMEX>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
+    case F_STAGE: hipLaunchKernelGGL((k_elem<2, P, F_STAGE, WPB, IMEX>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
+    case F_FINAL: hipLaunchKernelGGL((k_elem<2, P, F_FINAL, WPB, IMEX>), dim3(nblk), dim3(WPB * kWave), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -30,6 +30,7 @@ static hipError_t elem_pw(int mode, const StageArgs& a, int nblk, hipStream_t s)
 // wavefronts per workgroup: 1, 2 or 4 (cells per workgroup = wpb * 64 / P)
 template <int P>
 static hipError_t elem_p(int mode, int wpb, const StageArgs& a, int nblk, hipStream_t s) {
+  if (a.imex) return wpb == 1 ? elem_pw<P, 1, 1>(mode, a, nblk, s) : hipErrorInvalidValue;
   switch (wpb) {
     case 1: return elem_pw<P, 1>(mode, a, nblk, s);
     case 2: return elem_pw<P, 2>(mode, a, nblk, s);
