@@ -20,6 +20,10 @@ per-kernel events.  Besides the metric the line carries
   adjoint:      adjoint_128 gradient, backward vs forward time;
   imex:         the same beach case stepped with the IMEX pair (friction by
                 the TR-BDF2 companion) and with plain RK32, DoF-updates/s;
+  vortex:       the travelling vortex of Sec. 4.4 on the paper's finest static
+                mesh (640 x 320 cells) to T = 1/6 s with each scheme of its
+                table (RK32 r = 1, SSP3 r = 2, RK44 r = 3): wall time next to
+                the paper's CPU wall time for the same run (8 processes);
   cpu_baseline: the oracle timed on the host cores on a bounded window of
                 the same workload.
 """
@@ -325,6 +329,65 @@ def imex_bench(steps, warmup, device):
     return dict(workload="beach_dambreak_256", steps=steps, unit="DoF-updates/s", **out)
 
 
+# Wall times the paper reports for the static travelling vortex on its finest
+# mesh (n_max = 5, 2N x N cells with N = 320), T = 1/6 s, 8 CPU processes
+# (the table of the vortex section): scheme, r, seconds, DoFs (zeta + q).
+PAPER_VORTEX = [("rk32", 1, 386.9, 2_457_600), ("ssp3", 2, 1516.0, 5_529_600), ("rk44", 3, 3658.0, 9_830_400)]
+
+
+def vortex_bench(device, N=320):
+    """The travelling vortex (Sec. 4.4) on 2N x N cells over [0, 2] x [0, 1],
+    GLL rule with r + 2 nodes, exact state at the inflow, open outflow, walls,
+    fixed dt = T / ceil(T / (0.9 x the positivity bound at t = 0))."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from exact import Vortex
+    from workloads.gen import uniform_mesh_desc
+    from paper_2505_18743_amd import Solver
+    T = 1.0 / 6.0
+    v = Vortex()
+    out = []
+    for rk, r, paper_s, paper_dofs in PAPER_VORTEX:
+        mesh = uniform_mesh_desc(2 * N, N, 0.0, 0.0, 1.0 / N, bc=("state", "open", "wall", "wall"))
+        params = dict(r=r, S=(r + 2,), rule="gll", rk=rk, g=9.81, eps=1e-3, h_lim=0.0, eps0=1e-8, newton_max=20,
+                      cfl=0.9, cfl_mode=1, tracer=False, tide=(0.0, 1.0, 0.0, 0.0), adapt_degree=False)
+        s = Solver(mesh, params, device=device)
+        s.set_bathymetry(np.zeros(s.n_vol))
+        s.set_manning(np.zeros(s.n_cells))
+
+        def given(x, y):
+            h, u, w = v.fields(x, y, 0.0)
+            return h - 0.0, h * u, h * w, np.zeros_like(x)
+        s.set_boundary_state(given)
+        d = s.dof_coords()
+        h, u, w = v.fields(d[:, 0], d[:, 1], 0.0)
+        st = [h, h * u, h * w]
+        dtb = float(s.apply_operator(st[0], st[1], st[2], None, 0.0)[4].cpu()[0])
+        n = int(math.ceil(T / (0.9 * dtb)))
+        dt = T / n
+        s.set_state(*st)
+        s.run(3, dt)
+        s.sync()
+        s.set_state(*st)
+        s.set_time(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(n, dt)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        he, _, _ = v.fields(d[:, 0], d[:, 1], T)
+        z = s.get_state()[0].cpu().numpy()
+        err = float(np.sqrt(np.mean((z - he) ** 2)))
+        dofs = 3 * (r + 1) ** 2 * s.n_cells
+        out.append(dict(rk=rk, r=r, cells=s.n_cells, dofs=dofs, steps=n, dt=dt, wall_s=round(wall, 3),
+                        rms_zeta_error=err, paper_wall_s=paper_s, paper_dofs=paper_dofs,
+                        paper_hardware="8 CPU processes (deal.II, MPI), whole run"))
+        s.close()
+    return dict(workload="travelling_vortex_static_nmax5", T=T, runs=out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,7 +402,8 @@ def main():
     ap.add_argument("--elem-wpb", type=int, default=0, help="wavefronts per workgroup of the fast element kernel "
                     "(0: library default)")
     ap.add_argument("--imex-steps", type=int, default=100, help="beach steps of the IMEX leg (0: skip)")
-    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex"], default=None,
+    ap.add_argument("--no-vortex", action="store_true", help="skip the travelling-vortex wall-time leg")
+    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex", "vortex"], default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
@@ -366,6 +430,9 @@ def main():
         return
     if args.only == "imex":
         print(json.dumps(imex_bench(args.imex_steps, 3, dev)), flush=True)
+        return
+    if args.only == "vortex":
+        print(json.dumps(vortex_bench(dev)), flush=True)
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
@@ -473,6 +540,8 @@ def main():
         line["adjoint"] = adjoint_bench(dev)
     if args.imex_steps > 0:
         line["imex"] = imex_bench(args.imex_steps, 3, dev)
+    if not args.no_vortex:
+        line["vortex"] = vortex_bench(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     else:

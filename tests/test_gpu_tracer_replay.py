@@ -49,7 +49,7 @@ def replay(s, st, stages, end, dt):
     return s.get_state()
 
 
-@pytest.mark.parametrize("rk", ["ssp3", "rk32", "fe"])
+@pytest.mark.parametrize("rk", ["ssp3", "rk32", "fe", "imex"])
 def test_replay_equals_coupled_and_oracle(rk):
     say(f"case: tracer replay, hanging mesh + tide, {rk}, 12 steps, two tracers")
     o, b = hanging_case(2, (16, 8))
