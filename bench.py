@@ -410,8 +410,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
-              "(the multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the hot path on a single MI355X "
+              "and has no multi-GPU path (how it would shard is described in the design notes); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from workloads import workload
