@@ -587,6 +587,10 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.tracer = c->p.tracer ? 1 : 0;
   a.fric = 1;
   a.adapt = c->p.adapt_degree ? 1 : 0;
+  // contiguous cell ranges per XCD on single-level meshes; on quadtrees the
+  // cost per cell clusters by region (dry land, refinement), and the
+  // round-robin order balances it better across the XCDs
+  a.xmap = c->lv.size() == 1 ? 1 : 0;
   a.imex = c->imex ? 1 : 0;
   a.lres = c->d_lres;
   a.gam = c->d_gam;
@@ -625,6 +629,7 @@ FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st,
   a.gof = c->d_gof;
   a.ghost = c->d_ghost;
   a.ng = c->ng;
+  a.xmap = 1;
   return a;
 }
 

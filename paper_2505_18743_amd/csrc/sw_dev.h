@@ -72,6 +72,16 @@ __device__ __forceinline__ void rs_step(double* x, bool up) {
 // l*(V/P) .. l*(V/P) + V/P - 1 in x[0..V/P).  The partners lane ^ 16, ^ 15,
 // ^ 7, ^ 2, ^ 1 are taken from the high decision bit down, so partners always
 // hold the same subset of entries and the pairings span all P lanes.
+// Workgroup index remapped so that each of the 8 XCDs (workgroups are handed
+// out round robin over them) takes one contiguous range of the grid, where
+// neighbouring cells or faces share cache lines of the nodal blocks and the
+// sample rows stream from nearby HBM pages.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int X = 8;
+  const int q = n / X, rm = n % X, x = b % X, i = b / X;
+  return x * q + (x < rm ? x : rm) + i;
+}
+
 template <int P, int V>
 __device__ __forceinline__ void reduce_scatter(double* x, int lane) {
   static_assert(V % P == 0, "V must be a multiple of P");

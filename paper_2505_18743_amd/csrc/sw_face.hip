@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
   constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
   const int S = A.S;
   const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
-  const int fl = blockIdx.x * FPB + lf;
+  const int fl = (A.xmap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * FPB + lf;
   const bool fv = fl < A.nface;
   const int flc = fv ? fl : 0;
   const int f = A.face0 + flc;

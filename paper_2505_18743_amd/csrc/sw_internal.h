@@ -83,6 +83,7 @@ struct StageArgs {
   double a[4];           // combination weights a_{l,m} or b_m
   double g, eps, hlim, eps0;
   int newton_max, tracer, fric, adapt;
+  int xmap;              // 1: fast kernels give each XCD one contiguous range of cells
 };
 
 struct FaceArgs {
@@ -110,6 +111,7 @@ struct FaceArgs {
   int* err;
   double g, eps;
   int tracer;
+  int xmap;              // 1: each XCD takes one contiguous range of the class's faces
 };
 
 // ---- adjoint (vector-Jacobian products) ----------------------------------
