@@ -77,6 +77,14 @@ def element_stage_work(S, r, n_f, stage_terms):
     return 8.0 * words, float(flops)
 
 
+_T0 = time.perf_counter()
+
+
+def progress(what):
+    """One line on stderr as each part of the run starts (stdout keeps the JSON line)."""
+    print(f"bench: {time.perf_counter() - _T0:7.1f} s  {what}", file=sys.stderr, flush=True)
+
+
 def setup(wl, device):
     import numpy as np
     from paper_2505_18743_amd import Solver
@@ -349,6 +357,7 @@ def vortex_bench(device, N=320):
     v = Vortex()
     out = []
     for rk, r, paper_s, paper_dofs in PAPER_VORTEX:
+        progress(f"vortex {rk} r={r}")
         mesh = uniform_mesh_desc(2 * N, N, 0.0, 0.0, 1.0 / N, bc=("state", "open", "wall", "wall"))
         params = dict(r=r, S=(r + 2,), rule="gll", rk=rk, g=9.81, eps=1e-3, h_lim=0.0, eps0=1e-8, newton_max=20,
                       cfl=0.9, cfl_mode=1, tracer=False, tide=(0.0, 1.0, 0.0, 0.0), adapt_degree=False)
@@ -445,6 +454,7 @@ def main():
     nf = 3 + (1 if wl["params"]["tracer"] else 0)
     dofs_stage = nf * (r + 1) ** 2 * s.n_cells
 
+    progress(f"{args.workload}: warm-up")
     s.run(args.warmup)
     s.sync()
     reset()
@@ -456,6 +466,7 @@ def main():
         for _ in range(2):
             bcopy.copy_(a)
         torch.cuda.synchronize()
+    progress(f"{args.workload}: timed regions")
     # timed region 1: the whole step with no per-kernel events -> value
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -534,16 +545,22 @@ def main():
     line["config"]["max_newton_it"] = diag["max_newton_it"]
     line["config"]["r0_cells"] = diag["n_r0_cells"]
     if args.qt_steps > 0:
+        progress("quadtree")
         line["quadtree"] = quadtree_bench(args.qt_steps, 3, dev)
     if args.ens_steps > 0:
+        progress("ensemble")
         line["ensemble"] = ensemble_bench(args.ens_steps, 3, dev)
     if not args.no_adjoint:
+        progress("adjoint")
         line["adjoint"] = adjoint_bench(dev)
     if args.imex_steps > 0:
+        progress("imex")
         line["imex"] = imex_bench(args.imex_steps, 3, dev)
     if not args.no_vortex:
+        progress("vortex")
         line["vortex"] = vortex_bench(dev)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle on the host)")
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
