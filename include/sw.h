@@ -304,18 +304,26 @@ sw_status sw_sync(sw_ctx *c);
  * element kernel: value = wavefronts per
  * workgroup (1, 2 or 4; a workgroup holds value * 64 / P cells, P the power
  * of two >= S_L; default 1); kernel 1, the face kernel: value = lanes per
- * face (2, 4 or 8; the S_L face nodes are split over them; default 4).
+ * face (2, 4 or 8; the S_L face nodes are split over them; default 4);
+ * kernel 2, the order in which the fast element and tracer kernels hand cells
+ * to the 8 XCDs: value = 0 (round robin, workgroup i on XCD i mod 8), 1 (one
+ * contiguous range of cells per XCD) or -1 (default: 1 on single-level
+ * meshes, 0 on quadtrees; sw_get_workgroup reports the value in effect);
+ * results do not depend on it.
  * SW_EINVAL for other values.  sw_get_workgroup reads the current value. */
 sw_status sw_set_workgroup(sw_ctx *c, int32_t level, int32_t kernel, int32_t value);
 sw_status sw_get_workgroup(const sw_ctx *c, int32_t level, int32_t kernel, int32_t *value);
 /* Autotuner of the launch shape: times `steps` steps (after one untimed step)
- * with every pair (fast-kernel wavefronts per workgroup in {1, 2, 4}) x (face
- * lanes per face in {2, 4, 8}) on the context's current state, keeps the
- * fastest pair on every level and puts the state, degrees, times and time
+ * with every triple (fast-kernel wavefronts per workgroup in {1, 2, 4}) x
+ * (face lanes per face in {2, 4, 8}) x (element order over the XCDs in
+ * {0, 1}, as kernel 2 of sw_set_workgroup) on the context's current state,
+ * keeps the fastest triple on every level and puts the state, degrees, times and time
  * steps back as they were (the next step recomputes its start-of-step terms;
  * results are unchanged).  dt as sw_step.  Allocates a snapshot of the state
  * while it runs.  Outputs (host, may be NULL): the chosen pair.  Synchronises. */
 sw_status sw_autotune(sw_ctx *c, int32_t steps, double dt, int32_t *wpb_host, int32_t *lanes_host);
+/* The element order the last sw_autotune (or sw_set_workgroup kernel 2) set:
+ * read it with sw_get_workgroup(c, level, 2, &value). */
 
 /* ---- ensembles of independent members (not part of the paper's method) ----
  * sw_ens_create groups the members into batched contexts (sw_create_batch),
@@ -344,7 +352,9 @@ sw_status sw_ens_sync(sw_ens *e);
  * steps, on the batch's current state, which is restored).  cache_path (may
  * be NULL or empty): a text file of "<class> <wavefronts per workgroup>
  * <lanes per face>" lines, class "r<r>_S<S>"; classes found there are applied
- * without timing, new ones are timed and written back.  Synchronises. */
+ * without timing, new ones are timed and written back (the element order over
+ * the XCDs is tuned for the timed classes only; cached classes keep the
+ * default order).  Synchronises. */
 sw_status sw_ens_autotune(sw_ens *e, int32_t steps, const char *cache_path);
 
 #ifdef __cplusplus

@@ -441,7 +441,8 @@ class Solver:
     def set_workgroup(self, value, level=-1, kernel=0):
         """Launch shape: kernel 0 = fast element kernel, value = wavefronts
         per workgroup (1, 2, 4); kernel 1 = face kernel, value = lanes per face
-        (2, 4, 8)."""
+        (2, 4, 8); kernel 2 = fast-kernel cell order over the XCDs (0 round
+        robin, 1 contiguous ranges, -1 by the mesh)."""
         _check(load().sw_set_workgroup(self.h, int(level), int(kernel), int(value)), "sw_set_workgroup")
 
     def get_workgroup(self, level=0, kernel=0):
@@ -453,7 +454,7 @@ class Solver:
         """Time every launch shape on the current state, keep the fastest."""
         w, q = ctypes.c_int32(), ctypes.c_int32()
         _check(load().sw_autotune(self.h, int(steps), float(dt), ctypes.byref(w), ctypes.byref(q)), "sw_autotune")
-        return dict(elem_waves_per_workgroup=w.value, face_lanes=q.value)
+        return dict(elem_waves_per_workgroup=w.value, face_lanes=q.value, elem_order=self.get_workgroup(0, 2))
 
     def profile(self, on=True, kinds=None):
         """Kernel timing on/off; kinds: names of KERNELS to time (default all)."""

@@ -256,6 +256,8 @@ struct LevelH {
   int nblk = 0;              // general element-kernel blocks (one wavefront each)
   int wpb = 1;               // wavefronts per workgroup of the fast element kernel
   int face_q = kFaceLanes;   // lanes per face of the face kernel
+  int xorder = -1;           // fast-kernel cell order over the XCDs: 0 round robin, 1 contiguous,
+                             // -1 by the mesh (contiguous on single-level meshes)
   int8_t* d_wflag = nullptr;  // per wavefront (nblk): cells left to the general kernel
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
@@ -589,8 +591,8 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.adapt = c->p.adapt_degree ? 1 : 0;
   // contiguous cell ranges per XCD on single-level meshes; on quadtrees the
   // cost per cell clusters by region (dry land, refinement), and the
-  // round-robin order balances it better across the XCDs
-  a.xmap = c->lv.size() == 1 ? 1 : 0;
+  // round-robin order balances it better across the XCDs (unless set)
+  a.xmap = L.xorder >= 0 ? L.xorder : (c->lv.size() == 1 ? 1 : 0);
   a.imex = c->imex ? 1 : 0;
   a.lres = c->d_lres;
   a.gam = c->d_gam;
@@ -1705,11 +1707,13 @@ sw_status sw_set_workgroup(sw_ctx* c, int32_t level, int32_t kernel, int32_t val
     if (value != 1 && value != 2 && value != 4) return fail(SW_EINVAL, "wavefronts per workgroup must be 1, 2 or 4");
   } else if (kernel == 1) {
     if (value != 2 && value != 4 && value != 8) return fail(SW_EINVAL, "lanes per face must be 2, 4 or 8");
+  } else if (kernel == 2) {
+    if (value < -1 || value > 1) return fail(SW_EINVAL, "element order must be -1, 0 or 1");
   } else {
-    return fail(SW_EINVAL, "kernel must be 0 (fast element kernel) or 1 (face kernel)");
+    return fail(SW_EINVAL, "kernel must be 0 (fast element kernel), 1 (face kernel) or 2 (element order)");
   }
   for (auto& L : c->lv)
-    if (level < 0 || L.L == level) (kernel == 0 ? L.wpb : L.face_q) = value;
+    if (level < 0 || L.L == level) (kernel == 0 ? L.wpb : kernel == 1 ? L.face_q : L.xorder) = value;
   return SW_OK;
 }
 
@@ -1765,13 +1769,15 @@ sw_status sw_autotune(sw_ctx* c, int32_t steps, double dt, int32_t* wpb_out, int
   if (e == hipSuccess) e = hipEventCreate(&ea);
   if (e == hipSuccess) e = hipEventCreate(&eb);
   const int wpbs[3] = {1, 2, 4}, qs[3] = {2, 4, 8};
-  int bw = c->lv[0].wpb, bq = c->lv[0].face_q;
+  int bw = c->lv[0].wpb, bq = c->lv[0].face_q, bo = c->lv[0].xorder;
   float best = 1e30f;
+  for (int io = 0; io < 2 && e == hipSuccess && st == SW_OK; ++io)
   for (int iw = 0; iw < 3 && e == hipSuccess && st == SW_OK; ++iw)
     for (int iq = 0; iq < 3 && e == hipSuccess && st == SW_OK; ++iq) {
       for (auto& L : c->lv) {
         L.wpb = wpbs[iw];
         L.face_q = qs[iq];
+        L.xorder = io;
       }
       if ((e = restore()) != hipSuccess) break;
       if ((st = sw_step(c, dt)) != SW_OK) break;   // start-of-step terms and warm caches
@@ -1785,11 +1791,13 @@ sw_status sw_autotune(sw_ctx* c, int32_t steps, double dt, int32_t* wpb_out, int
         best = ms;
         bw = wpbs[iw];
         bq = qs[iq];
+        bo = io;
       }
     }
   for (auto& L : c->lv) {
     L.wpb = bw;
     L.face_q = bq;
+    L.xorder = bo;
   }
   if (e == hipSuccess && st == SW_OK) e = restore();
   if (ea) (void)hipEventDestroy(ea);
@@ -1808,7 +1816,9 @@ sw_status sw_get_workgroup(const sw_ctx* c, int32_t level, int32_t kernel, int32
   if (!c || !value) return fail(SW_EINVAL, "NULL argument");
   for (auto& L : c->lv)
     if (L.L == level) {
-      *value = kernel == 0 ? L.wpb : L.face_q;
+      *value = kernel == 0 ? L.wpb
+               : kernel == 1 ? L.face_q
+                             : (L.xorder >= 0 ? L.xorder : (c->lv.size() == 1 ? 1 : 0));
       return SW_OK;
     }
   return fail(SW_EINVAL, "no such level");

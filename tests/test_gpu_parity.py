@@ -319,9 +319,9 @@ def test_full_size_beach_sampled_residuals():
     assert worst < TOL_RHS
 
 
-@pytest.mark.parametrize("wpb,lanes", [(1, 2), (2, 8), (4, 4)])
-def test_launch_shapes_give_the_same_step(wpb, lanes):
-    say(f"case: launch shape wpb={wpb} lanes={lanes}, coastal_steps_16 + beach window, 10 steps")
+@pytest.mark.parametrize("wpb,lanes,order", [(1, 2, 0), (2, 8, 1), (4, 4, 0), (1, 4, 0)])
+def test_launch_shapes_give_the_same_step(wpb, lanes, order):
+    say(f"case: launch shape wpb={wpb} lanes={lanes} order={order}, coastal_steps_16 + beach window, 10 steps")
     for name, kw in (("coastal_steps_16", {}), ("beach_dambreak_256", dict(window=(116, 40, 24, 12)))):
         wl = workload(name, **kw)
         o, b = build_oracle(wl)
@@ -331,7 +331,9 @@ def test_launch_shapes_give_the_same_step(wpb, lanes):
             s_.set_state(*o.get_state())
         alt.set_workgroup(wpb, kernel=0)
         alt.set_workgroup(lanes, kernel=1)
+        alt.set_workgroup(order, kernel=2)
         assert alt.get_workgroup(0, 0) == wpb and alt.get_workgroup(0, 1) == lanes
+        assert alt.get_workgroup(0, 2) == order and ref.get_workgroup(0, 2) == 1
         ref.run(10)
         alt.run(10)
         ref.sync()
