@@ -601,24 +601,46 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   return a;
 }
 
-FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st, double cstage, int slot) {
+// Face launch of one conflict-free group over the levels whose face kernel
+// uses q lanes per face: direction dir (0: x faces, sides west/east; 1: y
+// faces), second = 0: conforming and boundary faces with the first hanging
+// sub-faces (classes 3 dir and 3 dir + 1, adjacent in the face order);
+// second = 1: the second hanging sub-faces (class 3 dir + 2).  A cell side
+// carries one face or two sub-faces, and sides of one direction touch disjoint
+// dofs, so no two faces of a group touch the same (cell, dof).  nblk: the
+// launch's workgroups (0: nothing to do).
+FaceArgs face_args(sw_ctx* c, int dir, int second, int q, const double* const* st, double cstage, int slot,
+                   int& nblk) {
   FaceArgs a{};
-  a.face0 = L.cface0[cls];
-  a.nface = L.cnface[cls];
   a.K = c->K;
-  a.S = L.S;
+  const int fpb = kWave / q, k0 = 3 * dir + (second ? 2 : 0);
+  int blk = 0, ns = 0;
+  for (auto& L : c->lv) {
+    if (L.face_q != q) continue;
+    const int n = second ? L.cnface[k0] : L.cnface[k0] + L.cnface[k0 + 1];
+    if (n == 0) continue;
+    a.sblk[ns] = blk;
+    a.sface0[ns] = L.cface0[k0];
+    a.snface[ns] = n;
+    a.sS[ns] = L.S;
+    a.sfl[ns] = L.tabs.fl;
+    a.sw[ns] = L.tabs.w;
+    a.szf[ns] = c->d_zf + L.zfoff + (size_t)(L.cface0[k0] - L.face0) * 2 * L.S;
+    blk += (n + fpb - 1) / fpb;
+    ++ns;
+  }
+  a.sblk[ns] = blk;
+  a.nseg = ns;
+  nblk = blk;
   a.fA = c->d_fA;
   a.fB = c->d_fB;
   a.meta = c->d_meta;
-  a.zf = c->d_zf + L.zfoff + (size_t)(L.cface0[cls] - L.face0) * 2 * L.S;
   for (int f = 0; f < 4; ++f) a.st[f] = st[f];
   a.res = c->d_res;
   a.slot = slot;
   a.cdx = c->d_cdx;
   a.cw1 = c->d_cw1;
   a.cmem = c->d_cmem;
-  a.fl = L.tabs.fl;
-  a.w = L.tabs.w;
   a.mt = c->d_mt;
   a.mdt = c->d_mdt;
   a.mtide = c->d_mtide;
@@ -635,20 +657,31 @@ FaceArgs face_args(sw_ctx* c, const LevelH& L, int cls, const double* const* st,
   return a;
 }
 
-// all face classes of all levels, adding into residual slot `slot`
+// all faces of all levels, adding into residual slot `slot`: x faces, then y
+// faces, each as the conforming/first-sub-face group and the second-sub-face
+// group (one launch per group and face-lane count)
 sw_status faces(sw_ctx* c, const double* const* st, double cstage, int slot, const double* mt_override = nullptr) {
+  std::vector<int> qs;
+  for (auto& L : c->lv)
+    if (std::find(qs.begin(), qs.end(), L.face_q) == qs.end()) qs.push_back(L.face_q);
   int n = 0;
-  for (auto& L : c->lv)
-    for (int k = 0; k < 6; ++k) n += L.cnface[k] > 0;
+  for (int dir = 0; dir < 2; ++dir)
+    for (int second = 0; second < 2; ++second)
+      for (int q : qs) {
+        int nblk = 0;
+        (void)face_args(c, dir, second, q, st, cstage, slot, nblk);
+        n += nblk > 0;
+      }
   sw_ctx::Scope sc(c, 3, n);
-  for (auto& L : c->lv)
-    for (int k = 0; k < 6; ++k) {
-      if (L.cnface[k] == 0) continue;
-      FaceArgs fa = face_args(c, L, k, st, cstage, slot);
-      if (mt_override) fa.mt = mt_override;
-      const int fpb = kWave / L.face_q;
-      HIPCHK(launch_face(c->r, L.face_q, fa, (L.cnface[k] + fpb - 1) / fpb, c->s));
-    }
+  for (int dir = 0; dir < 2; ++dir)
+    for (int second = 0; second < 2; ++second)
+      for (int q : qs) {
+        int nblk = 0;
+        FaceArgs fa = face_args(c, dir, second, q, st, cstage, slot, nblk);
+        if (nblk == 0) continue;
+        if (mt_override) fa.mt = mt_override;
+        HIPCHK(launch_face(c->r, q, fa, nblk, c->s));
+      }
   return SW_OK;
 }
 

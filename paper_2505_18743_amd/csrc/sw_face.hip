@@ -24,12 +24,18 @@ __device__ __forceinline__ int row_dof(int side, int k) {
 template <int R, int Q, int NQ>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 3 : 2))) void k_face(FaceArgs A) {
   constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
-  const int S = A.S;
   const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
-  const int fl = (A.xmap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * FPB + lf;
-  const bool fv = fl < A.nface;
+  const int bl = A.xmap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  int sg = 0;   // segment of this workgroup (uniform)
+  while (sg + 1 < A.nseg && bl >= A.sblk[sg + 1]) ++sg;
+  const int S = A.sS[sg];
+  const double* flt = A.sfl[sg];
+  const double* wt = A.sw[sg];
+  const double* zf = A.szf[sg];
+  const int fl = (bl - A.sblk[sg]) * FPB + lf;
+  const bool fv = fl < A.snface[sg];
   const int flc = fv ? fl : 0;
-  const int f = A.face0 + flc;
+  const int f = A.sface0[sg] + flc;
   int cA = A.fA[f], cB = A.fB[f];
   const int meta = A.meta[f];
   const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
   const double ny = sA == 2 ? -1.0 : (sA == 3 ? 1.0 : 0.0);
   const double g = A.g, eps = A.eps;
   const double dxA = A.cdx[cA];
-  const double* tB0 = A.fl + (size_t)(sub < 0 ? 0 : 1 + sub) * S * N1;
+  const double* tB0 = flt + (size_t)(sub < 0 ? 0 : 1 + sub) * S * N1;
   double zeta_b = 0.0, c_in = 0.0;
   // given boundary data (state: all of zeta, q, c; discharge: q and inflow c)
   const double* gd = nullptr;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
     double la[N1], lb[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      la[k] = A.fl[al * N1 + k];
+      la[k] = flt[al * N1 + k];
       lb[k] = tB0[al * N1 + k];
     }
     double vA[4] = {0.0, 0.0, 0.0, 0.0}, vB[4] = {0.0, 0.0, 0.0, 0.0};
@@ -99,8 +105,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
       vA[q] = sa;
       vB[q] = sb;
     }
-    const double zA = A.zf[((size_t)flc * 2 + 0) * S + al];
-    double zB = A.zf[((size_t)flc * 2 + 1) * S + al];
+    const double zA = zf[((size_t)flc * 2 + 0) * S + al];
+    double zB = zf[((size_t)flc * 2 + 1) * S + al];
     if (bnd) {
       zB = zA;
       if (bc == 0) {            // wall: mirror the normal discharge
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
     const double pres = 0.5 * g * 0.5 * (hsA + hsB) * (esA - esB);
     const double trac = 0.5 * ((qsxA * vA[3] + qsxB * vB[3]) * nx + (qsyA * vA[3] + qsyB * vB[3]) * ny) +
                         0.5 * lam * (hsA * vA[3] - hsB * vB[3]);
-    const double wl = A.w[al] * dxA;
+    const double wl = wt[al] * dxA;
     const double cAv[4] = {-mass, -momx + pres * nx, -momy + pres * ny, -trac};
     const double cBv[4] = {mass, momx + pres * nx, momy + pres * ny, trac};
 #pragma unroll

@@ -86,20 +86,28 @@ struct StageArgs {
   int xmap;              // 1: fast kernels give each XCD one contiguous range of cells
 };
 
+// One face launch covers a conflict-free group of faces (no two of them touch
+// the same (cell, dof)) over several levels: segment s is a level's run of
+// faces [sface0[s], sface0[s] + snface[s]) with that level's S, rule tables
+// and face samples, handled by workgroups [sblk[s], sblk[s + 1]).
+constexpr int kMaxSeg = 8;
 struct FaceArgs {
-  int face0, nface, K, S;
+  int K;
+  int nseg;
+  int sblk[kMaxSeg + 1];
+  int sface0[kMaxSeg], snface[kMaxSeg], sS[kMaxSeg];
+  const double* sfl[kMaxSeg];   // [3][S][N1] l_k at face nodes: s, s/2, (1+s)/2
+  const double* sw[kMaxSeg];    // [S] rule weights
+  const double* szf[kMaxSeg];   // [snface][2][S] face samples of the segment
   const int* fA;
   const int* fB;
   const int* meta;       // sideA | sideB<<2 | (sub+1)<<4 | boundary<<6 | bc<<8 (3 bits)
-  const double* zf;      // group block [nface][2][S]
   const double* st[4];
   double* res;           // [NS][4][K][NP] residual slots
   int slot;              // slot receiving the face terms
   const double* cdx;     // [K]
   const double* cw1;     // [K]
   const int* cmem;       // [K] member of each cell
-  const double* fl;      // [3][S][N1]
-  const double* w;       // [S]
   const double* mt;      // [M] time of each member at the start of the step
   const double* mdt;     // [M] time step of each member (unused when cstage = 0)
   const double* mtide;   // [M][4] tide amplitude, period, phase, inflow tracer
