@@ -26,16 +26,20 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
   constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
   const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
   const int bl = A.xmap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  int sg = 0;   // segment of this workgroup (uniform)
-  while (sg + 1 < A.nseg && bl >= A.sblk[sg + 1]) ++sg;
-  const int S = A.sS[sg];
-  const double* flt = A.sfl[sg];
-  const double* wt = A.sw[sg];
-  const double* zf = A.szf[sg];
-  const int fl = (bl - A.sblk[sg]) * FPB + lf;
-  const bool fv = fl < A.snface[sg];
+  // segment of this workgroup (uniform); a single-segment launch (one level)
+  // reads its parameters at fixed offsets, without the dependent lookup
+  int sg = 0;
+  if (A.nseg > 1)
+    while (sg + 1 < A.nseg && bl >= A.sblk[sg + 1]) ++sg;
+  const bool one = A.nseg == 1;
+  const int S = one ? A.sS[0] : A.sS[sg];
+  const double* flt = one ? A.sfl[0] : A.sfl[sg];
+  const double* wt = one ? A.sw[0] : A.sw[sg];
+  const double* zf = one ? A.szf[0] : A.szf[sg];
+  const int fl = (one ? bl : bl - A.sblk[sg]) * FPB + lf;
+  const bool fv = fl < (one ? A.snface[0] : A.snface[sg]);
   const int flc = fv ? fl : 0;
-  const int f = A.sface0[sg] + flc;
+  const int f = (one ? A.sface0[0] : A.sface0[sg]) + flc;
   int cA = A.fA[f], cB = A.fB[f];
   const int meta = A.meta[f];
   const int sA = meta & 3, sB = (meta >> 2) & 3, sub = ((meta >> 4) & 3) - 1;
