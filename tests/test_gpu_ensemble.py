@@ -52,10 +52,13 @@ def test_ensemble_groups_by_degree():
     ens.close()
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_ensemble_equals_one_by_one(graph):
-    say(f"case: ensemble vs one-by-one, graph={graph}, 6 small members, 8 steps")
+@pytest.mark.parametrize("graph,rk", [(True, None), (False, None), (True, "imex")])
+def test_ensemble_equals_one_by_one(graph, rk):
+    say(f"case: ensemble vs one-by-one, graph={graph}, rk={rk or 'members own'}, 6 small members, 8 steps")
     mem = small_members()
+    if rk is not None:
+        for w in mem:
+            w["params"] = dict(w["params"], rk=rk)
     ens, inputs = setup_ensemble(mem)
     ens.run(3, graph=graph)
     ens.run(5, graph=graph)
