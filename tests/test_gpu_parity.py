@@ -276,11 +276,10 @@ def test_edge_single_and_ragged_meshes(n):
         compare_states(o, s, TOL_STEP, f"{n}x{n} r={r}")
 
 
-def test_full_size_beach_sampled_residuals():
-    """256x256, r=2, 16x16 samples, as the benchmark launches it: the residual of
-    64 sampled cells against the oracle on the 3x3 patch around each."""
-    say("case: full-size beach_dambreak_256 sampled residuals")
+def full_beach(rk=None):
     wl = workload("beach_dambreak_256")
+    if rk is not None:
+        wl["params"] = dict(wl["params"], rk=rk)
     from paper_2505_18743_amd import Solver
     s = Solver(wl["mesh"], wl["params"], device="cuda:0")
     xy = s.node_coords()
@@ -290,7 +289,20 @@ def test_full_size_beach_sampled_residuals():
     dof = s.dof_coords()
     eta0 = wl["eta0"](dof[:, 0], dof[:, 1])
     s.init_lake_at_rest(eta0)
+    return s, wl, b
+
+
+def test_full_size_beach_sampled_residuals():
+    """256x256, r=2, 16x16 samples, as the benchmark launches it: the residual of
+    64 sampled cells against the oracle on the 3x3 patch around each."""
+    say("case: full-size beach_dambreak_256 sampled residuals")
+    s, wl, b = full_beach()
     s.run(10)
+    assert beach_sampled_worst(s, wl, b) < TOL_RHS
+    s.close()
+
+
+def beach_sampled_worst(s, wl, b):
     st = [t.clone() for t in s.get_state()]
     g = s.apply_operator(st[0], st[1], st[2], None, 0.0)
     s.sync()
@@ -316,7 +328,31 @@ def test_full_size_beach_sampled_residuals():
         for gg, rr, scale in zip(res, (F, Gx, Gy), scales):
             worst = max(worst, np.abs(gg[j, i] - rr[4]).max() / scale)
     say(f"  worst sampled rel err {worst:.3e}")
-    assert worst < TOL_RHS
+    return worst
+
+
+@pytest.mark.parametrize("rk,nsteps", [(None, 500), ("imex", 100)])
+def test_full_size_beach_whole_run(rk, nsteps):
+    """The benchmark's whole run (500 SSP3 steps of the 256x256 case; IMEX: 100
+    steps): at every step the positivity bound holds (no cell target below
+    roundoff: cells that are dry in exact arithmetic get targets like
+    -1.6e-24 m^3 from cancellation) and every value is finite; the total mass
+    (closed basin) is conserved to roundoff; at the end the operator still
+    matches the oracle on sampled patches."""
+    say(f"case: full-size beach_dambreak_256, {nsteps} steps, rk={rk or 'ssp3'}")
+    s, wl, b = full_beach(rk)
+    s.step()
+    s.sync()
+    m1 = s.diagnostics()["total_mass"]
+    for k in range(nsteps - 1):
+        s.step()
+        d = s.diagnostics()
+        assert d["min_target_mass"] >= -1e-12, (k, d)
+        assert d["nonfinite"] == 0, (k, d)
+    say(f"  mass {m1:.12e} -> {d['total_mass']:.12e}, t = {d['t']:.2f} s, cells of degree 0: {d['n_r0_cells']}")
+    assert d["total_mass"] == pytest.approx(m1, rel=1e-12)
+    assert beach_sampled_worst(s, wl, b) < TOL_RHS
+    s.close()
 
 
 @pytest.mark.parametrize("wpb,lanes,order", [(1, 2, 0), (2, 8, 1), (4, 4, 0), (1, 4, 0)])
