@@ -435,6 +435,18 @@ def test_full_size_tidal_quadtree_sampled_residuals():
     qy = 0.2 * np.cos(x / 2000.0 + 0.5) * np.sin(y / 3500.0)
     c = wl["tracer0"](x, y)
     t = 3000.0
+    worst, nh, nw = quadtree_sampled_worst(s, wl, b, [eta, qx, qy, c], t)
+    assert nh == 8 and nw == 4
+    assert worst < TOL_RHS
+    s.close()
+
+
+def quadtree_sampled_worst(s, wl, b, state, t):
+    """Worst sampled residual error of the quadtree context s at `state`
+    against the oracle on 3x3 coarse-cell windows (every level, cells at
+    hanging faces, cells on the tidal side)."""
+    d = wl["mesh"]
+    eta, qx, qy, c = state
     g = s.apply_operator(eta, qx, qy, c, t)
     s.sync()
     K, NP = s.n_cells, s.np_
@@ -481,5 +493,33 @@ def test_full_size_tidal_quadtree_sampled_residuals():
             worst = max(worst, np.abs(gg[k] - rr[w]).max() / scale)
     say(f"  {len(picks)} sampled cells ({len(hang)} at hanging faces, {len(west)} on the tidal side), "
         f"worst rel err {worst:.3e}")
-    assert len(hang) == 8 and len(west) == 4
+    return worst, len(hang), len(west)
+
+
+def test_full_size_tidal_quadtree_whole_run():
+    """The quadtree workload's whole run (1000 coupled steps with tracer and
+    tide): finite values and positivity to roundoff along the run, then the
+    operator at the final state against the oracle on sampled windows."""
+    say("case: full-size tidal_quadtree_r3, 1000 steps")
+    from paper_2505_18743_amd import Solver
+    wl = workload("tidal_quadtree_r3")
+    d = wl["mesh"]
+    s = Solver(d, wl["params"], device="cuda:0")
+    xy = s.node_coords()
+    b = wl["bed"](xy[:, 0], xy[:, 1])
+    del xy
+    s.set_bathymetry(b)
+    s.set_manning(wl["manning"])
+    dof = s.dof_coords()
+    s.init_lake_at_rest(wl["eta0"](dof[:, 0], dof[:, 1]))
+    st = s.get_state()
+    s.set_state(st[0], st[1], st[2], wl["tracer0"](dof[:, 0], dof[:, 1]))
+    for k in range(20):
+        s.run(50)
+        dg = s.diagnostics()
+        assert dg["nonfinite"] == 0 and dg["min_target_mass"] >= -1e-12, (k, dg)
+    say(f"  t = {dg['t']:.1f} s after {dg['step']} steps, cells of degree 0: {dg['n_r0_cells']}")
+    st = [x.detach().cpu().numpy() for x in s.get_state()]
+    worst, nh, nw = quadtree_sampled_worst(s, wl, b, st, dg["t"])
     assert worst < TOL_RHS
+    s.close()
