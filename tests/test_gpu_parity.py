@@ -250,17 +250,19 @@ def test_lake_at_rest_init_matches_oracle():
     assert rel(cpu(s.get_state()[0], K), o.get_state()[0]) < 1e-15
 
 
-@pytest.mark.parametrize("n", [1, 3, 5])
-def test_edge_single_and_ragged_meshes(n):
-    """1x1, 3x3, 5x5 meshes (cell counts not multiples of the cells per block), S=3 and S=5."""
-    say(f"case: ragged {n}x{n}")
+@pytest.mark.parametrize("n,rk", [(1, "ssp3"), (3, "ssp3"), (5, "ssp3"), (1, "imex"), (5, "imex")])
+def test_edge_single_and_ragged_meshes(n, rk):
+    """1x1, 3x3, 5x5 meshes (cell counts not multiples of the cells per block), S=3 and S=5;
+    with the IMEX pair under Manning friction too."""
+    say(f"case: ragged {n}x{n}, {rk}")
     m = Mesh.uniform(n, n, 0.0, 0.0, 10.0)
     for (r, S) in ((1, 3), (2, 5)):
-        p = Params(r=r, S=(S,), rule="gll", rk="ssp3", eps=1e-3, h_lim=1e-3, cfl=0.2)
+        p = Params(r=r, S=(S,), rule="gll", rk=rk, eps=1e-3, h_lim=1e-3, cfl=0.2)
         o = Oracle(m, p)
         xy = o.node_coords()
         b = -1.0 - 0.2 * np.sin(xy[:, 0] / 7.0) * np.cos(xy[:, 1] / 5.0)
         o.set_bathymetry(b)
+        o.set_manning(np.full(m.K, 0.05 if rk == "imex" else 0.0))
         rng = np.random.default_rng(n + r)
         K, npn = m.K, (r + 1) ** 2
         st = [rng.uniform(-0.1, 0.1, (K, npn)), rng.uniform(-0.2, 0.2, (K, npn)), rng.uniform(-0.2, 0.2, (K, npn))]
