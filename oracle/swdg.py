@@ -58,7 +58,9 @@ ambiguous or garbled (each one is also listed in the design notes):
     from h(zeta^n) on the rule nodes; mu_K >= h_lim keeps degree r.  A cell
     going from r to 0 is remapped conservatively: zeta-bar solves
     Hbar(zeta-bar) = Hbar(zeta^n), q-bar is the cell mean, c-bar = int(hc)/Hbar.
-  * Tracer in a dry cell (Hbar = 0): keeps its start-of-step value.
+  * Tracer in a dry cell keeps its start-of-step value.  A cell counts as dry
+    when Hbar <= 1e-12 eps |K|: zero up to the round-off water that the dry
+    lift of eq:initial_guess and the scalar solve of Hbar = 0 can leave.
 """
 from __future__ import annotations
 
@@ -807,17 +809,18 @@ class Oracle:
         """hc-mass system (eq:algebraic_concentration, eq:mass_matrix_concentration)."""
         W, Bv = lv.W, lv.Bv
         Hbar = (W * h).sum(1)
+        wet = Hbar > 1e-12 * self.p.eps * lv.dx ** 2   # dry up to round-off water
         Hm = torch.einsum("kq,qi,qj->kij", W * h, Bv, Bv)
         x, ok = self._chol_solve(Hm, CT)
         # constant-mode fallback: c = c_keep + s with sum_i (Hm (c_keep + s))_i = sum CT
         Hc = torch.einsum("kij,kj->ki", Hm, c_keep).sum(1)
-        safe = torch.where(Hbar > 0, Hbar, torch.ones_like(Hbar))
+        safe = torch.where(wet, Hbar, torch.ones_like(Hbar))
         s = (CT.sum(1) - Hc) / safe
         fb = c_keep + s[:, None]
         cbar = CT.sum(1) / safe
         out = torch.where((full & ok)[:, None], x, fb)
         out = torch.where(full[:, None], out, cbar[:, None].expand_as(out))
-        return torch.where((Hbar > 0)[:, None], out, c_keep)
+        return torch.where(wet[:, None], out, c_keep)
 
     # -- one time step ------------------------------------------------------
     def step(self, dt=None):
@@ -854,7 +857,8 @@ class Oracle:
                 znew, _, _, _, _, _ = self._newton(lv, rpos, Tn, zguess, full0)
                 hc = (lv.W * h[remap] * (c[ridx] @ lv.Bv.T)).sum(1)
                 cmean = c[ridx] @ self.mean_w
-                cbar = torch.where(Hbar > 0, hc / torch.where(Hbar > 0, Hbar, torch.ones_like(Hbar)), cmean)
+                wet = Hbar > 1e-12 * p.eps * lv.dx ** 2
+                cbar = torch.where(wet, hc / torch.where(wet, Hbar, torch.ones_like(Hbar)), cmean)
                 zeta[ridx] = znew[:, :1].expand(-1, self.np_)
                 qx[ridx] = (qx[ridx] @ self.mean_w)[:, None].expand(-1, self.np_)
                 qy[ridx] = (qy[ridx] @ self.mean_w)[:, None].expand(-1, self.np_)

@@ -525,3 +525,32 @@ def test_full_size_tidal_quadtree_whole_run():
     worst, nh, nw = quadtree_sampled_worst(s, wl, b, st, dg["t"])
     assert worst < TOL_RHS
     s.close()
+
+
+@pytest.mark.parametrize("rk", ["ssp3", "imex"])
+def test_all_dry_domain(rk):
+    """A domain dry everywhere, 5 fixed-dt steps with tracer and friction: the
+    surface the dry lift and the scalar solve leave matches the oracle; depth,
+    discharge and tracer stay at rest to roundoff; nothing becomes non-finite."""
+    say(f"case: all-dry 4x3 mesh, r=2, {rk}")
+    from test_oracle_properties import all_dry_case
+    o, b = all_dry_case(rk)
+    s = gpu_from_oracle(o, b)
+    s.set_state(*o.get_state())
+    for _ in range(5):
+        o.step(1.0)
+        s.step(1.0)
+    s.sync()
+    K = o.m.K
+    got = [cpu(x, K) for x in s.get_state()]
+    ref = o.get_state()
+    e = rel(got[0], ref[0])
+    say(f"  zeta rel err {e:.3e}, max |q| {max(np.abs(got[1]).max(), np.abs(got[2]).max()):.2e}, "
+        f"max |c - 0.7| {np.abs(got[3] - 0.7).max():.2e}")
+    assert e < TOL_STEP
+    assert all(np.all(np.isfinite(v)) for v in got)
+    assert np.abs(got[1]).max() < 1e-25 and np.abs(got[2]).max() < 1e-25
+    assert np.abs(got[3] - 0.7).max() < 1e-14
+    dg = s.diagnostics()
+    assert dg["n_r0_cells"] == K and abs(dg["total_mass"]) < 1e-13 and dg["nonfinite"] == 0
+    s.close()
