@@ -216,6 +216,37 @@ def test_steps_hanging_tracer_elev(rk):
     compare_states(o, s, TOL_STEP, "20 steps")
 
 
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_wide_sample_rules_hanging_tracer(r):
+    """20x20 samples on the coarse cells and 10x10 on the refined ones: the
+    fast kernels run with 32 and 16 lanes per cell.  One residual evaluation
+    and 10 SSP3 steps with tracer and tide against the oracle."""
+    say(f"case: hanging mesh r={r} S=(20, 10)")
+    o, b = hanging_case(r, (20, 10))
+    s = gpu_from_oracle(o, b)
+    st0 = o.get_state()
+    K = o.m.K
+    rng = np.random.default_rng(20 + r)
+    st = [st0[0], rng.uniform(-0.5, 0.5, st0[0].shape), rng.uniform(-0.5, 0.5, st0[0].shape), st0[3]]
+    F, Gx, Gy, R, dtb = o.apply_operator(st, 700.0)
+    g = s.apply_operator(st[0], st[1], st[2], st[3], 700.0)
+    s.sync()
+    for name, gg, rr in (("F", g[0], F), ("Gx", g[1], Gx), ("Gy", g[2], Gy), ("R", g[3], R)):
+        e = rel(cpu(gg, K), rr)
+        say(f"  {name} rel err {e:.3e}")
+        assert e < TOL_RHS, (r, name, e)
+    s.set_state(*st0)
+    s.profile(True)
+    s.kernel_time_reset()
+    run_both(o, s, 10)
+    launches = s.kernel_times()["element_stage"][1]
+    s.profile(False)
+    say(f"  fast stage kernel launches: {launches}")
+    assert launches > 0
+    compare_states(o, s, TOL_STEP, f"10 steps r={r}")
+    s.close()
+
+
 def test_stage_by_stage_matches_step():
     say("case: step split into begin / rk_stage / end")
     wl = workload("coastal_steps_16")
