@@ -544,6 +544,12 @@ def main():
                 roofline=roof)
     line["config"]["max_newton_it"] = diag["max_newton_it"]
     line["config"]["r0_cells"] = diag["n_r0_cells"]
+    # the paper's DoF count with degree-0 cells as one dof per field (their
+    # number at the end of the timed steps)
+    nr0 = int(diag["n_r0_cells"])
+    active = nf * ((r + 1) ** 2 * (s.n_cells - nr0) + nr0)
+    line["active"] = dict(dofs_per_stage=active, value=active * stages * args.steps / (ms * 1e-3),
+                          unit="DoF-updates/s")
     if args.qt_steps > 0:
         progress("quadtree")
         line["quadtree"] = quadtree_bench(args.qt_steps, 3, dev)
