@@ -85,6 +85,28 @@ def progress(what):
     print(f"bench: {time.perf_counter() - _T0:7.1f} s  {what}", file=sys.stderr, flush=True)
 
 
+def copy_roof(device, mib=1024, reps=10):
+    """Attainable HBM bandwidth on this GPU: a device-to-device copy of `mib`
+    MiB (read plus write) through the runtime's copy kernel, event-timed."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device=device)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
 def setup(wl, device):
     import numpy as np
     from paper_2505_18743_amd import Solver
@@ -536,6 +558,8 @@ def main():
                 algo_bytes_per_launch=bytes_launch,
                 algo_flops_per_launch=flops_launch, hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4),
                 kernel_share={k: round(v[0] / ms3, 4) for k, v in kt3.items()})
+    copy_gbs = copy_roof(dev)
+    roof.update(copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(gbs / copy_gbs, 4))
     line = dict(metric="FP64 DoF-updates/s per RK stage", value=value, unit="DoF-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
