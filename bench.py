@@ -558,8 +558,10 @@ def main():
                 algo_bytes_per_launch=bytes_launch,
                 algo_flops_per_launch=flops_launch, hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4),
                 kernel_share={k: round(v[0] / ms3, 4) for k, v in kt3.items()})
-    copy_gbs = copy_roof(dev)
-    roof.update(copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(gbs / copy_gbs, 4))
+    # (not in counter runs: their own calibration copies must be the only ones)
+    if not args.calibrate_copy:
+        copy_gbs = copy_roof(dev)
+        roof.update(copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(gbs / copy_gbs, 4))
     line = dict(metric="FP64 DoF-updates/s per RK stage", value=value, unit="DoF-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
