@@ -116,7 +116,8 @@ typedef struct {
   int64_t n_pos_viol;        /* (cell, stage) pairs with negative target mass           */
   int32_t max_newton_it;     /* largest Newton iteration count in the last step          */
   int32_t nonfinite;         /* 1 if a non-finite value was found in the state           */
-  int64_t n_r0_cells;        /* cells at degree 0 in the last step                       */
+  int64_t n_r0_cells;        /* cells at degree 0 for the next step (the degree decision  */
+                             /* of eq:criteria_p, taken at the end of the last step)       */
   int64_t n_fallback;        /* masked Jacobians replaced by the constant-mode update    */
   int64_t step;              /* steps taken                                              */
 } sw_diag;

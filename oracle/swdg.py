@@ -44,6 +44,12 @@ ambiguous or garbled (each one is also listed in the design notes):
   * Rusanov speed uses the unreconstructed depths (eq:lxf_parameter).
   * Friction is explicit, added to the discharge residual, with the
     desingularised depth (eq:discharge_rhs_implicit with an explicit RK).
+    With the IMEX pair the residual L keeps the desingularised depth and the
+    friction-modified discharge matrix (eq:mass_matrix_discharge) takes the
+    plain depth h of the previous stage, as printed; a dry node (h = 0) adds
+    nothing to that matrix.  A cell whose friction-modified matrix fails the
+    Cholesky pivot test below takes the degree-0 (constant-mode) discharge
+    update for that stage.
   * Newton stop (eq:newton and the text after eq:mass_matrix): the paper stops
     on an l1 increment below 1e-16.  Because H is piecewise linear in zeta,
     an iterate whose land-sea mask equals the previous iterate's mask is the
@@ -822,20 +828,15 @@ class Oracle:
         out = torch.where(full[:, None], out, cbar[:, None].expand_as(out))
         return torch.where(wet[:, None], out, c_keep)
 
-    # -- one time step ------------------------------------------------------
-    def step(self, dt=None):
-        """One explicit RK step in Butcher form (Sec. 3.1, eq:algebraic_elevation,
-        eq:algebraic_discharge, eq:algebraic_concentration)."""
+    def _adapt(self, zeta, qx, qy, c, flag):
+        """Degree decision at a step start (eq:criteria_p): r_K = 0 iff the
+        smallest depth over the rule nodes is below h_lim; a cell going from r
+        to 0 is remapped conservatively in place (zeta-bar solves
+        Hbar(zeta-bar) = Hbar(zeta^n), q-bar is the cell mean, c-bar =
+        int(h c)/Hbar).  Returns the new flags."""
         p = self.p
-        A, b, cc = tableau(p.rk)
-        imp = implicit_tableau(p.rk)     # IMEX: friction with the DIRK companion
-        s = len(b)
-        zeta, qx, qy, c = [x.clone() for x in self.state]
         r = p.r
-        K = self.m.K
-        diag = dict(min_target=float("inf"), n_viol=0, newton_it=0, n_fallback=0)
-        # ---- degree adaptation (eq:criteria_p) and conservative remap ----
-        newflag = self.flag.clone()
+        newflag = flag.clone()
         for lv in self.levels:
             pos = torch.arange(len(lv.idx))
             h, mask, H = self._depth_terms(lv, pos, zeta[lv.idx])
@@ -844,7 +845,7 @@ class Oracle:
                              torch.zeros_like(mu, dtype=torch.long)) if p.adapt_degree else \
                 torch.full((len(lv.idx),), r, dtype=torch.long)
             newflag[lv.idx] = nf
-            remap = (self.flag[lv.idx] == r) & (nf == 0)
+            remap = (flag[lv.idx] == r) & (nf == 0)
             if bool(remap.any()):
                 ridx = lv.idx[remap]
                 rpos = pos[remap]
@@ -863,6 +864,34 @@ class Oracle:
                 qx[ridx] = (qx[ridx] @ self.mean_w)[:, None].expand(-1, self.np_)
                 qy[ridx] = (qy[ridx] @ self.mean_w)[:, None].expand(-1, self.np_)
                 c[ridx] = cbar[:, None].expand(-1, self.np_)
+        return newflag
+
+    def adapted(self):
+        """The state and degree flags as the next step sees them after its
+        degree decision and remap (the oracle's own state is left unchanged):
+        what a caller that fuses the next step's start into the end of a step
+        holds."""
+        st = [x.clone() for x in self.state]
+        flag = self._adapt(st[0], st[1], st[2], st[3], self.flag)
+        return [x.numpy() for x in st], flag.numpy()
+
+    def adapted_state(self):
+        return self.adapted()[0]
+
+    # -- one time step ------------------------------------------------------
+    def step(self, dt=None):
+        """One explicit RK step in Butcher form (Sec. 3.1, eq:algebraic_elevation,
+        eq:algebraic_discharge, eq:algebraic_concentration)."""
+        p = self.p
+        A, b, cc = tableau(p.rk)
+        imp = implicit_tableau(p.rk)     # IMEX: friction with the DIRK companion
+        s = len(b)
+        zeta, qx, qy, c = [x.clone() for x in self.state]
+        r = p.r
+        K = self.m.K
+        diag = dict(min_target=float("inf"), n_viol=0, newton_it=0, n_fallback=0)
+        # ---- degree adaptation (eq:criteria_p) and conservative remap ----
+        newflag = self._adapt(zeta, qx, qy, c, self.flag)
         self.flag = newflag
         full_all = newflag == r
         # ---- start-of-step quantities H^n, Q~^n, C~^n ----
@@ -882,6 +911,7 @@ class Oracle:
         res = []
         lres = []                        # IMEX: implicit-part residuals L of each stage
         cur = state_n
+        self.last_stages = [state_n]     # stage states u^(1) = u^n, u^(2), ..., then u^(n+1)
         t0 = self.t
         for l in range(s + 1):
             if l > 0:
@@ -929,18 +959,14 @@ class Oracle:
                 # discharge (eq:algebraic_discharge with A = exact mass matrix; for
                 # an IMEX stage A^(l) = M + a~_ll dt Gam(q^(l-1), h^(l-1)),
                 # eq:mass_matrix_discharge, the previous stage's friction)
-                Amat, Asum = Mq, Jac
                 if imp is not None and l < s and imp[0][l][l] != 0.0:
                     _, _, Gam = self._friction(cur)
-                    Amat = Mq + (imp[0][l][l] * dt) * Gam
-                    Asum = Jac + (imp[0][l][l] * dt) * Gam.sum((1, 2))
-                qxf = torch.linalg.solve(Amat, QX.unsqueeze(-1)).squeeze(-1)
-                qyf = torch.linalg.solve(Amat, QY.unsqueeze(-1)).squeeze(-1)
-                qx0 = (QX.sum(1) / Asum)[:, None].expand_as(qxf)
-                qy0 = (QY.sum(1) / Asum)[:, None].expand_as(qyf)
-                nqx = torch.where(full_all[:, None], qxf, qx0)
-                nqy = torch.where(full_all[:, None], qyf, qy0)
+                    nqx, nqy, qfb = self._discharge_solve(Mq, Jac, Gam, imp[0][l][l] * dt, QX, QY, full_all)
+                else:
+                    nqx, nqy, qfb = self._discharge_solve(Mq, Jac, None, 0.0, QX, QY, full_all)
+                diag["n_fallback"] += int(qfb.sum())
                 cur = [nz, nqx, nqy, nc]
+                self.last_stages.append(cur)
             if l < s:
                 F, Gx, Gy, R, dtb = self.residual(cur, t0 + cc[l] * (dt if dt is not None else 0.0),
                                                   friction=imp is None)
@@ -961,12 +987,40 @@ class Oracle:
         diag.update(dt=dt, mass=mass, n_r0=int((self.flag == 0).sum()))
         return diag
 
+    def _discharge_solve(self, Mq, Jac, Gam, ct, QX, QY, full):
+        """Discharge solve of a stage (eq:algebraic_discharge): A q = Q with A
+        the exact mass matrix M times |K| (Table 1), or for an IMEX stage
+        A = M + ct Gam (eq:mass_matrix_discharge, ct = a~_ll dt; Gam None: no
+        implicit part).  A degree-0 cell takes the constant
+        q = sum_i Q_i / (|K| + ct sum_ij Gam_ij), the same equation tested with
+        the constant function.  The matrix is SPD; a Cholesky pivot below
+        1e-14 trace (friction weights beyond the reach of double precision, at
+        roundoff-thin nodes) gives that constant-mode update too.
+        Returns (qx, qy, fallback) per cell."""
+        if Gam is None:
+            Amat, Asum = Mq, Jac
+        else:
+            Amat = Mq + ct * Gam
+            Asum = Jac + ct * Gam.sum((1, 2))
+        qxf, ok = self._chol_solve(Amat, QX)
+        qyf, _ = self._chol_solve(Amat, QY)
+        fb = full & ~ok
+        use = (full & ok)[:, None]
+        qx0 = (QX.sum(1) / Asum)[:, None].expand_as(qxf)
+        qy0 = (QY.sum(1) / Asum)[:, None].expand_as(qyf)
+        return torch.where(use, qxf, qx0), torch.where(use, qyf, qy0), fb
+
     def _friction(self, state, nman=None):
-        """Implicit-part terms of the discharge equation at a state:
-        L_i = -int gamma q psi_i (eq:discharge_rhs_implicit) and the matrix
-        Gam_ij = int gamma psi_i psi_j of eq:mass_matrix_discharge, with
-        gamma = g n^2 |q| / h_des^(7/3) at the sample nodes (eq:manning with the
-        desingularised depth of eq:velocity, as L uses)."""
+        """Implicit-part terms of the discharge equation at a state.
+
+        L_i = -int gamma(|q|, h_des) q psi_i (eq:discharge_rhs_implicit: the
+        desingularised depth of eq:velocity) and the matrix
+        Gam_ij = int gamma(|q|, h) psi_i psi_j of eq:mass_matrix_discharge with
+        the plain depth h, gamma(q, h) = g n^2 q / h^(7/3) (eq:manning), both on
+        the sample rule.  At a dry node (h = 0) the friction coefficient of the
+        matrix is taken as zero: the node carries no water column, so it adds
+        nothing to the matrix (gamma q -> 0 there).  For h >= eps the two depths
+        coincide (h_des = h)."""
         p = self.p
         zeta, qx, qy = state[0], state[1], state[2]
         nman = self.nman if nman is None else nman
@@ -982,11 +1036,15 @@ class Oracle:
             qxq, qyq = qx[idx] @ lv.Bv.T, qy[idx] @ lv.Bv.T
             h = _pos(zq + self.zb_eff(lv, None))
             ih = _inv_des(h, p.eps)
-            gam = p.g * nman[idx][:, None] ** 2 * _safe_norm(qxq, qyq) * ih ** (7.0 / 3.0)
+            gn2q = p.g * nman[idx][:, None] ** 2 * _safe_norm(qxq, qyq)
+            gam_des = gn2q * ih ** (7.0 / 3.0)                     # gamma(|q|, h_des)
+            live = (h > 0) & (gn2q > 0)
+            hs = torch.where(live, h, torch.ones_like(h))
+            gam_h = torch.where(live, gn2q / hs ** (7.0 / 3.0), torch.zeros_like(h))   # gamma(|q|, h)
             W, Bv = lv.W, lv.Bv
-            Lx[idx] = -((W * gam * qxq) @ Bv)
-            Ly[idx] = -((W * gam * qyq) @ Bv)
-            Gam[idx] = torch.einsum("kq,qi,qj->kij", W * gam, Bv, Bv)
+            Lx[idx] = -((W * gam_des * qxq) @ Bv)
+            Ly[idx] = -((W * gam_des * qyq) @ Bv)
+            Gam[idx] = torch.einsum("kq,qi,qj->kij", W * gam_h, Bv, Bv)
         return Lx, Ly, Gam
 
     def apply_operator(self, state=None, t=None):
@@ -1000,6 +1058,22 @@ class Oracle:
             h, _, _ = self._depth_terms(lv, torch.arange(len(lv.idx)), self.state[0][lv.idx])
             mass += float((lv.W * h).sum())
         return mass
+
+    def conserved(self, state=None):
+        """Per-dof depth and tracer-mass integrals H_i = int psi_i h and
+        C_i = int psi_i h c (eq:depth_rhs, eq:concentration_rhs) of a state
+        (default: the current one), and the cell means Hbar_K / |K|."""
+        st = self.state if state is None else [torch.as_tensor(np.asarray(x, dtype=np.float64)).reshape(self.m.K, self.np_)
+                                               for x in state]
+        H = torch.zeros(self.m.K, self.np_, dtype=DT)
+        C = torch.zeros(self.m.K, self.np_, dtype=DT)
+        for lv in self.levels:
+            pos = torch.arange(len(lv.idx))
+            h, _, Hl = self._depth_terms(lv, pos, st[0][lv.idx])
+            H[lv.idx] = Hl
+            C[lv.idx] = (lv.W * h * (st[3][lv.idx] @ lv.Bv.T)) @ lv.Bv
+        mean_depth = H.sum(1) / torch.as_tensor(self.m.dx ** 2)
+        return H.numpy(), C.numpy(), mean_depth.numpy()
 
     def depth_integrals(self):
         """Per-cell Hbar_K and per-dof H_i at the current state."""

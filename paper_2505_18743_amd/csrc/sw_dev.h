@@ -200,4 +200,23 @@ __device__ __forceinline__ void pointwise(double h, double qx, double qy, double
   }
 }
 
+// gamma(|q|, h) = g n^2 |q| h^{-7/3} of eq:manning at the plain depth h, the
+// coefficient of the friction-modified discharge matrix
+// (eq:mass_matrix_discharge).  For h >= eps it equals the desingularised value
+// gam_des that pointwise() returns (h_des = h there); below eps it is
+// (1/h)^2 h^{-1/3}, with h scaled by an exact power of two before the cube
+// root when it is below the range of the single-precision start; a dry node
+// (h = 0) or a node without discharge gives zero.
+__device__ __forceinline__ double gamma_plain(double h, double qx, double qy, double eps, double gn2, bool fric,
+                                              double gam_des) {
+  if (h >= eps) return gam_des;
+  const double q2 = qx * qx + qy * qy;
+  if (!fric || !(h > 0.0) || !(q2 > 0.0)) return 0.0;
+  const double qn = q2 * rsq_nr(q2);
+  const double ih = rcp_nr(h);
+  const bool tiny = h < 0x1p-96;
+  const double c = tiny ? rcbrt_nr(h * 0x1p96) * 0x1p32 : rcbrt_nr(h);
+  return gn2 * qn * (ih * ih) * c;
+}
+
 }  // namespace swk
