@@ -206,6 +206,20 @@ sw_status sw_set_time(sw_ctx *c, double t);
 sw_status sw_apply_operator(sw_ctx *c, const double *eta, const double *qx, const double *qy,
                             const double *tracer, double t, double *F, double *Gx, double *Gy,
                             double *R, double *dtb_dev);
+/* The same evaluation for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid it): same
+ * arguments, same kernels and results, but the call's scratch (one residual
+ * slot of 4 n_dofs doubles, the per-face time-step bounds and their reduction
+ * partials, rounded up to 256 bytes each) lives in a fixed 48 MiB device array
+ * of the library (6 Mi doubles, one per GPU, held until the process ends)
+ * instead of the context's memory; it calls no allocator.  SW_EINVAL when the
+ * context needs more scratch than that (above about 1.5 M dofs per field,
+ * 165k cells at r = 2; use sw_apply_operator).  Every call on one GPU shares that array:
+ * calls that overlap on the device (other streams or threads, other contexts)
+ * race and must be ordered by the caller. */
+sw_status sw_apply_operator_noalloc(sw_ctx *c, const double *eta, const double *qx, const double *qy,
+                                    const double *tracer, double t, double *F, double *Gx, double *Gy,
+                                    double *R, double *dtb_dev);
 
 /* One RK step split in its parts (Sec. 3.1, Butcher form):
  *   sw_step_begin: degree adaptation + conservative remap, H(zeta^n), C~^n,

@@ -21,6 +21,7 @@ RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3, "imex": 4}
 EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_cell_map", "sw_counts",
            "sw_node_coords", "sw_dof_coords", "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset",
            "sw_set_state", "sw_get_state", "sw_init_lake_at_rest", "sw_set_time", "sw_apply_operator",
+           "sw_apply_operator_noalloc",
            "sw_step_begin", "sw_rk_stage", "sw_step_end", "sw_step", "sw_run", "sw_diagnostics",
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
@@ -106,6 +107,7 @@ def load():
     L.sw_init_lake_at_rest.argtypes = [vp, vp]
     L.sw_set_time.argtypes = [vp, ctypes.c_double]
     L.sw_apply_operator.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
+    L.sw_apply_operator_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
     L.sw_step_begin.argtypes = [vp, ctypes.c_double]
     L.sw_rk_stage.argtypes = [vp, ctypes.c_int32]
     L.sw_step_end.argtypes = [vp]
@@ -377,6 +379,25 @@ class Solver:
         _check(load().sw_apply_operator(self.h, *[_ptr(x) for x in ins], _ptr(tc), float(t),
                                         *[_ptr(x) for x in outs], _ptr(dtb)), "sw_apply_operator")
         return outs[0], outs[1], outs[2], outs[3], dtb
+
+    def apply_operator_noalloc(self, eta, qx, qy, c, t, out):
+        """sw_apply_operator_noalloc: the residuals of sw_apply_operator with the
+        call's device scratch in the library's fixed array (no allocation by
+        the library).  eta, qx, qy, c: device float64 [n_dofs] (c may be None
+        without a tracer); out = (F, Gx, Gy, R, dtb): caller-owned device
+        float64 tensors ([n_dofs] each, R may be None without a tracer; dtb [1]
+        or None), written in place."""
+        ins = [self._dev(a, self.n_dofs) for a in (eta, qx, qy)]
+        tc = self._dev(c, self.n_dofs) if c is not None else None
+        for o in out:
+            if o is not None and (not o.is_cuda or o.dtype != torch.float64 or not o.is_contiguous()
+                                  or o.device != self.dev):
+                raise ValueError("outputs must be contiguous float64 tensors on the solver's device")
+        for o in out[:4]:
+            if o is not None and o.numel() != self.n_dofs:
+                raise ValueError("residual outputs must hold n_dofs values")
+        _check(load().sw_apply_operator_noalloc(self.h, *[_ptr(x) for x in ins], _ptr(tc), float(t),
+                                                *[_ptr(x) for x in out]), "sw_apply_operator_noalloc")
 
     def step_begin(self, dt=0.0):
         _check(load().sw_step_begin(self.h, float(dt)), "sw_step_begin")

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -806,6 +807,38 @@ sw_status need_inputs(const sw_ctx* c) {
 
 }  // namespace
 
+// Device scratch of sw_apply_operator_noalloc, one copy per GPU for the life
+// of the process (48 MiB).  Host code never passes `scratch` itself to a
+// kernel: its name is a host-side stand-in, and each device's address is
+// fetched once (scratch_setup, from sw_create with that device current) and
+// kept in g_scratch[device].
+constexpr size_t kScratchDoubles = (size_t)6 << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// the current device's copy of the scratch array (hipGetSymbolAddress, once)
+sw_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SW_EINVAL, "device index out of the library's range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return SW_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(SW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[dev] = static_cast<double*>(ptr);
+  return SW_OK;
+}
+
+double* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[dev];
+}
+}  // namespace
+
 extern "C" {
 
 const char* sw_last_error(void) { return g_err.c_str(); }
@@ -855,6 +888,11 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   {
     hipError_t e = hipGetDevice(&c->dev);
     if (e != hipSuccess) return bail(SW_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    // the device scratch of sw_apply_operator_noalloc on this device
+    if (scratch_setup(c->dev) != SW_OK) {
+      delete c;
+      return SW_EHIP;
+    }
   }
   c->p = *p;
   c->M = n_members;
@@ -1410,16 +1448,39 @@ sw_status sw_set_time(sw_ctx* c, double t) {
   return SW_OK;
 }
 
-sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, const double* qy, const double* tr,
-                            double t, double* F, double* Gx, double* Gy, double* R, double* dtb) {
-  if (!c) return fail(SW_EINVAL, "NULL context");
-  if (!eta || !qx || !qy || !F || !Gx || !Gy) return fail(SW_EINVAL, "state and residual pointers must be non-NULL");
-  if (c->p.tracer && (!tr || !R)) return fail(SW_EINVAL, "tracer and R are required with a tracer");
-  sw_status st = need_inputs(c);
-  if (st != SW_OK) return st;
-  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_apply_operator cannot run inside an open step");
+namespace {
+// The operator evaluation's own device scratch: the residual slot that the
+// volume and face kernels accumulate into (res, slot `slot`), the members'
+// boundary time (mt), the per-face time-step bounds (fdt), the chunk partials
+// of their reduction (part) and the per-member bound (mtmp).
+struct ApplyBufs {
+  double* res;
+  int slot;
+  double* mt;
+  double* fdt;
+  double* part;
+  double* mtmp;
+};
+
+sw_status apply_impl(sw_ctx* c, const double* eta, const double* qx, const double* qy, const double* tr, double t,
+                     double* F, double* Gx, double* Gy, double* R, double* dtb, const ApplyBufs& b) {
+  // the helpers below read the context's buffers: point them at b for the
+  // launches of this call (kernel arguments are taken at launch)
+  struct Swap {
+    sw_ctx* c;
+    double *res, *fdt, *part;
+    ~Swap() {
+      c->d_res = res;
+      c->d_fdt = fdt;
+      c->d_part = part;
+    }
+  } keep{c, c->d_res, c->d_fdt, c->d_part};
+  c->d_res = b.res;
+  c->d_fdt = b.fdt;
+  c->d_part = b.part;
+  sw_status st;
   // the elevation boundary is evaluated at t (stage offset 0)
-  hipLaunchKernelGGL(k_fill_n, dim3((c->M + 255) / 256), dim3(256), 0, c->s, c->d_mt_apply, c->M, t);
+  hipLaunchKernelGGL(k_fill_n, dim3((c->M + 255) / 256), dim3(256), 0, c->s, b.mt, c->M, t);
   HIPCHK(hipGetLastError());
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
@@ -1428,14 +1489,14 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
     a.in[1] = qx;
     a.in[2] = qy;
     a.in[3] = c->p.tracer ? tr : nullptr;
-    a.slot = kApplySlot;
+    a.slot = b.slot;
     HIPCHK(launch_stage(c->r, L.P, M_APPLY, a, L.nblk, c->s));
   }
   const double* st4[4] = {eta, qx, qy, c->p.tracer ? tr : eta};
-  if ((st = faces(c, st4, 0.0, kApplySlot, c->d_mt_apply)) != SW_OK) return st;
+  if ((st = faces(c, st4, 0.0, b.slot, b.mt)) != SW_OK) return st;
   for (auto& L : c->lv) {
     StageArgs a = stage_args(c, L);
-    a.slot = kApplySlot;
+    a.slot = b.slot;
     a.out[0] = F;
     a.out[1] = Gx;
     a.out[2] = Gy;
@@ -1444,12 +1505,59 @@ sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, cons
   }
   if (dtb) {
     // bare positivity bound, minimum over the members
-    if ((st = reduce_dt(c, nullptr, c->d_mtmp)) != SW_OK) return st;
-    hipLaunchKernelGGL(k_min_all, dim3(1), dim3(256), 0, c->s, c->d_mtmp, c->M, dtb);
+    if ((st = reduce_dt(c, nullptr, b.mtmp)) != SW_OK) return st;
+    hipLaunchKernelGGL(k_min_all, dim3(1), dim3(256), 0, c->s, b.mtmp, c->M, dtb);
     HIPCHK(hipGetLastError());
   }
+  return SW_OK;
+}
+
+sw_status apply_checks(sw_ctx* c, const double* eta, const double* qx, const double* qy, const double* tr, double* F,
+                       double* Gx, double* Gy, double* R) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!eta || !qx || !qy || !F || !Gx || !Gy) return fail(SW_EINVAL, "state and residual pointers must be non-NULL");
+  if (c->p.tracer && (!tr || !R)) return fail(SW_EINVAL, "tracer and R are required with a tracer");
+  sw_status st = need_inputs(c);
+  if (st != SW_OK) return st;
+  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_apply_operator cannot run inside an open step");
+  return SW_OK;
+}
+}  // namespace
+
+sw_status sw_apply_operator(sw_ctx* c, const double* eta, const double* qx, const double* qy, const double* tr,
+                            double t, double* F, double* Gx, double* Gy, double* R, double* dtb) {
+  sw_status st = apply_checks(c, eta, qx, qy, tr, F, Gx, Gy, R);
+  if (st != SW_OK) return st;
+  const ApplyBufs b{c->d_res, kApplySlot, c->d_mt_apply, c->d_fdt, c->d_part, c->d_mtmp};
+  if ((st = apply_impl(c, eta, qx, qy, tr, t, F, Gx, Gy, R, dtb, b)) != SW_OK) return st;
   c->start_ready = false;   // the apply slot does not disturb the step's data, but stay safe
   return SW_OK;
+}
+
+sw_status sw_apply_operator_noalloc(sw_ctx* c, const double* eta, const double* qx, const double* qy,
+                                    const double* tr, double t, double* F, double* Gx, double* Gy, double* R,
+                                    double* dtb) {
+  sw_status st = apply_checks(c, eta, qx, qy, tr, F, Gx, Gy, R);
+  if (st != SW_OK) return st;
+  double* base = scratch_address(c->dev);
+  if (!base) return fail(SW_EINVAL, "the device scratch of this context's device was not set up by sw_create");
+  // layout, each part rounded up to 32 doubles (256 bytes): one residual slot,
+  // member times, face bounds, chunk partials, member bounds
+  const size_t KN = (size_t)c->K * c->NP;
+  auto up = [](size_t n) { return (n + 31) / 32 * 32; };
+  const size_t nres = up(4 * KN), nmt = up((size_t)c->M), nfdt = up((size_t)c->F),
+               npart = up((size_t)std::max(c->nfch, c->ncch) * D_NSLOT), nmtmp = up((size_t)c->M);
+  const size_t need = nres + nmt + nfdt + npart + nmtmp;
+  if (need > kScratchDoubles)
+    return fail(SW_EINVAL, "sw_apply_operator_noalloc: this context needs " + std::to_string(need) +
+                               " doubles of device scratch, more than the library's fixed " +
+                               std::to_string(kScratchDoubles) + " (use sw_apply_operator)");
+  // every word a launch reads is written earlier in the same call (volume
+  // kernel before the faces, face bounds before their reduction), so nothing
+  // left by a previous call is read
+  const ApplyBufs b{base, 0, base + nres, base + nres + nmt, base + nres + nmt + nfdt,
+                    base + nres + nmt + nfdt + npart};
+  return apply_impl(c, eta, qx, qy, tr, t, F, Gx, Gy, R, dtb, b);
 }
 
 sw_status sw_step_begin(sw_ctx* c, double dt) {
