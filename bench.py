@@ -42,6 +42,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (and matrix) peak
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every 4
+# cycles at 2.4 GHz (FP64 FMA: 16 lanes x 2 flops x 4 SIMDs x 256 CUs x 2.4 GHz
+# = 78.6 TFLOP/s)
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_CYCLES = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "element_stage_beach_dambreak_256.traffic.json")
 STAGE_SOURCES = ["sw_stage.inc", "sw_dev.h", "sw_internal.h", "sw_stage_r2.hip"]
 
@@ -77,6 +83,85 @@ def element_stage_work(S, r, n_f, stage_terms):
     return 8.0 * words, float(flops)
 
 
+def tracer_stage_work(S, r, stage_terms):
+    """Algorithmic bytes and flops per cell of one launch of the fast tracer
+    kernel of a stage (tracer target, h-weighted matrix from one pass over
+    the samples, Cholesky solve, tracer volume residual of the new state):
+
+    bytes = 8 [ S^2                      bathymetry samples
+              + 3 NP                     zeta, qx, qy of the stage
+              + 2 NP                     c^n, C~^n
+              + NP m                     m stored tracer residuals
+              + 2 NP ]                   new c and its residual written
+    flops = S^2 [ 2 (r+1)                zeta at the node
+              + 2 NX                     x-pair partials of int h psi_i psi_j
+              + 2 (r+1) 3                qx, qy, c at the node
+              + 2 (r+1) 2 ]              residual accumulations
+            + 2 S NT + NP^3 / 3 + 2 NP^2 assembly along y, factorisation, solves
+    with NP = (r+1)^2, NX = (r+1)(r+2)/2, NT = NP (NP+1)/2.
+    """
+    NP = (r + 1) ** 2
+    NX = (r + 1) * (r + 2) // 2
+    NT = NP * (NP + 1) // 2
+    words = S * S + NP * (7 + stage_terms)
+    flops = S * S * (2 * (r + 1) + 2 * NX + 6 * (r + 1) + 4 * (r + 1)) + 2 * S * NT + NP ** 3 / 3 + 2 * NP * NP
+    return 8.0 * words, float(flops)
+
+
+def lanes_for(S):
+    """Lanes per cell of the element kernels: the power of two >= S (at least 4)."""
+    P = 4
+    while P < S:
+        P <<= 1
+    return P
+
+
+def read_counters(path, sha):
+    """A counter record of profiles/ taken on the current kernel sources (else None)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    return tr if tr.get("source_sha") == sha else None
+
+
+def roofline(bytes_launch, flops_launch, launch_s, counters, kernel):
+    """Roofline of one kernel launch.  achieved = algorithmic bytes (flops) per
+    launch / launch time.  The bound is the resource the counters show busier:
+    HBM (counter bytes / launch time against the 8 TB/s peak) or VALU issue
+    (VALU instructions x 4 cycles against 1,024 SIMDs at 2.4 GHz); an
+    issue-bound kernel reports its FP64 rate against the FP64 peak ("alu").
+    Without a counter record for the current sources the larger of the two
+    algorithmic fractions decides."""
+    gbs = bytes_launch / launch_s / 1e9
+    tfl = flops_launch / launch_s / 1e12
+    f_hbm, f_fp = gbs / HBM_PEAK_GBS, tfl / FP64_PEAK_TFLOPS
+    traffic = issue = hbm_counter = None
+    if counters:
+        traffic = counters.get("bytes_per_launch")
+        if traffic:
+            hbm_counter = traffic / launch_s / 1e9 / HBM_PEAK_GBS
+        vi = counters.get("valu_insts_per_launch")
+        if vi:
+            issue = vi * VALU_CYCLES / (N_SIMD * CLOCK_HZ * launch_s)
+    if issue is not None and hbm_counter is not None:
+        alu = issue > hbm_counter
+        basis = "counters"
+    else:
+        alu = f_fp > f_hbm
+        basis = "algorithmic fractions (no counter record for these sources)"
+    if alu:
+        roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=round(f_fp, 4))
+    else:
+        roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(f_hbm, 4))
+    roof.update(traffic=traffic, kernel=kernel, launch_ms=round(launch_s * 1e3, 5),
+                algo_bytes_per_launch=bytes_launch, algo_flops_per_launch=flops_launch,
+                hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4), bound_from=basis,
+                valu_issue_frac=None if issue is None else round(issue, 4),
+                hbm_frac_counters=None if hbm_counter is None else round(hbm_counter, 4))
+    return roof
+
+
 _T0 = time.perf_counter()
 
 
@@ -107,6 +192,19 @@ def copy_roof(device, mib=1024, reps=10):
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
+def calibration_copy(mib, device):
+    """Two device-to-device copies of `mib` MiB: a kernel of known traffic for
+    scaling the HBM counters of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=device)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def setup(wl, device):
     import numpy as np
     from paper_2505_18743_amd import Solver
@@ -128,30 +226,50 @@ def setup(wl, device):
     return s, reset, np.asarray(b)
 
 
-def cpu_baseline(name, seconds):
-    """The oracle (PyTorch CPU, float64) on a 24x12-cell window of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, window=(96, 96, 64, 64)):
+    """The oracle (PyTorch CPU, float64) on the host: one SSP3 step of the
+    whole mesh after one warm-up step with every host thread torch uses, and
+    one step of a 64x64 window of it after a warm-up step on one thread."""
     import torch
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import build_oracle
     from workloads import workload
-    wl = workload(name, window=(116, 40, 24, 12)) if name == "beach_dambreak_256" else workload(name)
-    o, _ = build_oracle(wl)
     from oracle import tableau
-    stages = len(tableau(o.p.rk)[1])
-    nf = 3 + (1 if o.p.tracer else 0)
-    dofs = nf * o.np_ * o.m.K
-    o.step()                      # warm-up
-    t0 = time.perf_counter()
-    n = 0
-    while True:
+
+    def rate(wl, threads):
+        torch.set_num_threads(threads)
+        o, _ = build_oracle(wl)
+        stages = len(tableau(o.p.rk)[1])
+        dofs = (3 + (1 if o.p.tracer else 0)) * o.np_ * o.m.K
+        o.step()                      # warm-up
+        t0 = time.perf_counter()
         o.step()
-        n += 1
         el = time.perf_counter() - t0
-        if el > seconds:
-            break
-    return dict(value=dofs * stages * n / el, unit="DoF-updates/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"oracle on a {o.m.K}-cell window (24x12) of {name}, {n} SSP3 steps after 1 warm-up step, "
-                       f"{el:.1f} s")
+        return dofs * stages / el, el, o.m.K
+
+    threads = torch.get_num_threads()
+    full, el_full, K_full = rate(workload(name), threads)
+    progress("cpu baseline: one thread")
+    one, el_one, K_one = rate(workload(name, window=window) if name == "beach_dambreak_256" else workload(name), 1)
+    torch.set_num_threads(threads)
+    return dict(value=full, unit="DoF-updates/s", cores=threads, kind="oracle",
+                sample=f"oracle on the whole {name} mesh ({K_full} cells), 1 SSP3 step after 1 warm-up step, "
+                       f"{el_full:.1f} s, {threads} threads",
+                nproc=os.cpu_count(), cpu_model=cpu_model(),
+                one_core=dict(value=one, unit="DoF-updates/s", cores=1,
+                              sample=f"oracle on a {K_one}-cell window (64x64) of {name}, 1 SSP3 step after 1 "
+                                     f"warm-up step, {el_one:.1f} s, 1 thread"))
 
 
 def quadtree_bench(steps, warmup, device):
@@ -188,21 +306,57 @@ def quadtree_bench(steps, warmup, device):
     kt = s.kernel_times()
     s.profile(False)
     s.close()
+    # roofline of the heavier of the stage-mode element and tracer kernels:
+    # their launches over the timed steps (one per level and stage) against
+    # the algorithmic bytes and flops of every cell of every level
+    r = int(wl["params"]["r"])
+    Ss = wl["params"]["S"]
+    lev = wl["mesh"]["level"]
+    per_level = [int((lev == L).sum()) for L in range(len(Ss))]
+    mean_terms = sum(range(1, stages)) / max(stages - 1, 1)
+    calls = steps * (stages - 1)
+    cand = {}
+    for name, work in (("element_stage", lambda S: element_stage_work(S, r, 3, mean_terms)),
+                       ("element_tracer", lambda S: tracer_stage_work(S, r, mean_terms))):
+        t_ms, n = kt[name]
+        if n == 0:
+            continue
+        b = sum(k * work(S)[0] for k, S in zip(per_level, Ss)) * calls
+        f = sum(k * work(S)[1] for k, S in zip(per_level, Ss)) * calls
+        cand[name] = (t_ms, b, f, n)
+    roof = None
+    if cand:
+        name = max(cand, key=lambda k: cand[k][0])
+        t_ms, b, f, n = cand[name]
+        kname = "k_elem" if name == "element_stage" else "k_trc"
+        kernel = f"{kname}<r={r},P={'/'.join(str(lanes_for(S)) for S in Ss)},F_STAGE> (one launch per level)"
+        counters = read_counters(os.path.join(ROOT, "profiles", f"{name}_tidal_quadtree_r3.traffic.json"),
+                                 stage_source_sha())
+        # per stage: the launches of all levels together
+        roof = roofline(b / calls, f / calls, t_ms * 1e-3 / calls, counters, kernel)
+        roof.update(launches=n, scope="all levels of one stage per launch group")
     return dict(workload="tidal_quadtree_r3", cells=s.n_cells, steps=steps, ms_per_step=ms / steps,
                 value=dofs_stage * stages * steps / (ms * 1e-3), unit="DoF-updates/s",
                 fields=4, r0_cells=diag["n_r0_cells"], max_newton_it=diag["max_newton_it"],
-                kernel_share={k: round(v[0] / ms2, 4) for k, v in kt.items()})
+                kernel_share={k: round(v[0] / ms2, 4) for k, v in kt.items()}, roofline=roof)
 
 
-def ensemble_bench(steps, warmup, device):
+def ensemble_bench(steps, warmup, device, eager_only=False):
     """64-member ensemble (uneven meshes, r in {1,2,3}): batched and graph-
-    replayed vs the same members as 64 contexts stepped one after another."""
+    replayed vs the same members as 64 contexts stepped one after another.
+    eager_only: just `steps` eager batched steps with the default launch
+    shapes (for a profiler)."""
     import torch
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import member_solver, setup_ensemble
     from workloads import workload
     mem = workload("ensemble_64")
     ens, inputs = setup_ensemble(mem, device)
+    if eager_only:
+        ens.run(steps, graph=False)
+        ens.sync()
+        ens.close()
+        return dict(workload="ensemble_64", members=len(mem), steps=steps, mode="eager, default launch shapes")
     tuned = ens.autotune(steps=3)      # launch shape per degree class (state restored)
     stages = 3
     dofs = sum(3 * (w["params"]["r"] + 1) ** 2 * len(w["mesh"]["level"]) for w in mem)
@@ -253,8 +407,19 @@ def ensemble_bench(steps, warmup, device):
     for o in ones:
         o.close()
     ens.close()
+    # the batches run on streams of their own and overlap, so the roofline is
+    # that of the whole graph-replayed step: the element kernels' algorithmic
+    # bytes and flops (begin, stages, final: s launches a step) of every member
+    # over the step time
+    bts = sum(len(w["mesh"]["level"]) * element_stage_work(16, w["params"]["r"], 3, 1.0)[0] for w in mem) * stages
+    fls = sum(len(w["mesh"]["level"]) * element_stage_work(16, w["params"]["r"], 3, 1.0)[1] for w in mem) * stages
+    step_s = res["graph"] / steps
+    roof = roofline(bts, fls, step_s, read_counters(os.path.join(ROOT, "profiles", "ensemble_64.traffic.json"),
+                                                    stage_source_sha()),
+                    "k_elem<r=1|2|3,P=16> of all batches, whole step")
+    roof.update(scope="element kernels' algorithmic work per step over the step time (batches overlap)")
     return dict(workload="ensemble_64", members=len(mem), cells=cells, dofs_per_stage=dofs, steps=steps,
-                value=dofs * stages * steps / res["graph"], unit="DoF-updates/s",
+                value=dofs * stages * steps / res["graph"], unit="DoF-updates/s", roofline=roof,
                 ms_per_step=res["graph"] / steps * 1e3, eager_ms_per_step=res["eager"] / steps * 1e3,
                 one_by_one_ms_per_step=res["one_by_one"] / steps * 1e3,
                 speedup_vs_one_by_one=res["one_by_one"] / res["graph"],
@@ -426,8 +591,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="beach_dambreak_256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=300, help="ensemble_64 steps per mode (0: skip)")
+    ap.add_argument("--ens-eager-only", action="store_true",
+                    help="with --only ensemble: eager batched steps only (for a profiler)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint_128 gradient timing")
     ap.add_argument("--qt-steps", type=int, default=100, help="tidal_quadtree_r3 steps (0: skip)")
     ap.add_argument("--elem-wpb", type=int, default=0, help="wavefronts per workgroup of the fast element kernel "
@@ -451,8 +617,10 @@ def main():
         print("bench.py needs a GPU (HIP device)", file=sys.stderr)
         sys.exit(1)
     dev = "cuda:0"
+    if args.only and args.calibrate_copy:
+        calibration_copy(args.calibrate_copy, dev)
     if args.only == "ensemble":
-        print(json.dumps(ensemble_bench(args.ens_steps, 3, dev)), flush=True)
+        print(json.dumps(ensemble_bench(args.ens_steps, 3, dev, eager_only=args.ens_eager_only)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(adjoint_bench(dev)), flush=True)
@@ -482,12 +650,7 @@ def main():
     reset()
     s.sync()
     if args.calibrate_copy:
-        n = args.calibrate_copy * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device=dev)
-        bcopy = torch.empty_like(a)
-        for _ in range(2):
-            bcopy.copy_(a)
-        torch.cuda.synchronize()
+        calibration_copy(args.calibrate_copy, dev)
     progress(f"{args.workload}: timed regions")
     # timed region 1: the whole step with no per-kernel events -> value
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -537,30 +700,14 @@ def main():
     # stages 2..s combine 1..s-1 stored residuals: average
     mean_terms = sum(range(1, stages)) / max(stages - 1, 1)
     bpc, fpc = element_stage_work(S, r, nf, mean_terms)
-    bytes_launch = bpc * s.n_cells
-    flops_launch = fpc * s.n_cells
-    gbs = bytes_launch / avg_s / 1e9
-    tfl = flops_launch / avg_s / 1e12
-    f_hbm, f_fp = gbs / HBM_PEAK_GBS, tfl / FP64_PEAK_TFLOPS
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("source_sha") == stage_source_sha():
-            traffic = tr.get("bytes_per_launch")
-    if f_hbm >= f_fp:
-        roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(f_hbm, 4))
-    else:
-        roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(f_fp, 4))
-    roof.update(traffic=traffic, kernel=f"k_elem<r={r},P={S},F_STAGE>",
-                launch_ms=round(avg_s * 1e3, 5), launches=k_n, timed_region_ms=round(ms2, 3),
-                algo_bytes_per_launch=bytes_launch,
-                algo_flops_per_launch=flops_launch, hbm_frac=round(f_hbm, 4), fp64_frac=round(f_fp, 4),
+    roof = roofline(bpc * s.n_cells, fpc * s.n_cells, avg_s, read_counters(TRAFFIC_FILE, stage_source_sha()),
+                    f"k_elem<r={r},P={lanes_for(S)},F_STAGE>")
+    roof.update(launches=k_n, timed_region_ms=round(ms2, 3),
                 kernel_share={k: round(v[0] / ms3, 4) for k, v in kt3.items()})
     # (not in counter runs: their own calibration copies must be the only ones)
     if not args.calibrate_copy:
         copy_gbs = copy_roof(dev)
+        gbs = roof["algo_bytes_per_launch"] / avg_s / 1e9
         roof.update(copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(gbs / copy_gbs, 4))
     line = dict(metric="FP64 DoF-updates/s per RK stage", value=value, unit="DoF-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=ms / args.steps, higher_is_better=True,
@@ -593,7 +740,7 @@ def main():
         line["vortex"] = vortex_bench(dev)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host)")
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.workload)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -300,8 +300,10 @@ sw_status sw_member_diagnostics(const sw_ctx *c, int32_t member, sw_diag *out_ho
  *   kind 2: fast element kernel of the final combination (+ next step's start)
  *   kind 3: face kernel
  *   kind 4: general element kernel (cells the fast kernel leaves, tracer replays)
- *   kind 5: fast tracer kernel (tracer solve, C~ and tracer residual of the cells
- *           the fast element kernel keeps).
+ *   kind 5: fast tracer kernel of stages 2..s (tracer solve and tracer residual of
+ *           the cells the fast element kernel keeps)
+ *   kind 6: fast tracer kernel at step begin and of the final combination (+ C~ of
+ *           the next step).
  * sw_kernel_time_reset clears the totals.  on = 0: off; 1: every class;
  * on = 1 | (mask << 1) with mask != 0: only the classes whose bit is set in
  * mask (fewer events, less perturbation).  The events are timing-only (no

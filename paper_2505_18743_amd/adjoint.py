@@ -80,6 +80,9 @@ class ObservedRun(torch.autograd.Function):
                 obs.add_adjoint(sbar[0], gout[n])
                 s.vjp_step(stages[i], ctx.t0 + n * dt, dt, sbar, nbar, dbar)
         ctx.ckpt = None
+        # the step adjoint is exact only in the all-wet regime; a stage state
+        # outside it is flagged on the device and raises here
+        s.sync()
         return nbar, dbar, None, None, None, None, None, None, None
 
 

@@ -390,8 +390,7 @@ class Solver:
         ins = [self._dev(a, self.n_dofs) for a in (eta, qx, qy)]
         tc = self._dev(c, self.n_dofs) if c is not None else None
         for o in out:
-            if o is not None and (not o.is_cuda or o.dtype != torch.float64 or not o.is_contiguous()
-                                  or o.device != self.dev):
+            if o is not None and (not self._on_dev(o) or o.dtype != torch.float64 or not o.is_contiguous()):
                 raise ValueError("outputs must be contiguous float64 tensors on the solver's device")
         for o in out[:4]:
             if o is not None and o.numel() != self.n_dofs:
@@ -430,6 +429,11 @@ class Solver:
     def n_stages(self):
         return {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4, "imex": 3}[self.params.get("rk", "ssp3")]
 
+    def _on_dev(self, x):
+        """x is a tensor on the solver's GPU."""
+        return (torch.is_tensor(x) and x.device.type == "cuda"
+                and (self.dev.index is None or x.device.index == self.dev.index))
+
     def _flow_buf(self, x, n, what):
         if (not torch.is_tensor(x) or x.numel() != n * 3 * self.n_dofs or not x.is_contiguous()
                 or x.dtype != torch.float64 or x.device.type != "cuda"):
@@ -452,10 +456,17 @@ class Solver:
 
     def vjp_step(self, stages, t, dt, state_bar, n_bar, db_bar):
         """Adjoint of one recorded step: state_bar [3, n_dofs] updated in place
-        (adjoint of u^(n+1) -> of u^n); n_bar, db_bar [n_cells] accumulated."""
+        (adjoint of u^(n+1) -> of u^n); n_bar, db_bar [n_cells] accumulated.
+        Every array is a device tensor on the solver's device (the kernels
+        read and write them directly)."""
+        self._flow_buf(stages, self.n_stages(), "stages")
+        if not self._on_dev(stages):
+            raise ValueError("stages must live on the solver's device")
         for x, n in ((state_bar, 3 * self.n_dofs), (n_bar, self.n_cells), (db_bar, self.n_cells)):
-            if x.numel() != n or not x.is_contiguous() or x.dtype != torch.float64:
-                raise ValueError("adjoint arrays must be contiguous float64 of the right size")
+            if (not torch.is_tensor(x) or x.numel() != n or not x.is_contiguous() or x.dtype != torch.float64
+                    or not self._on_dev(x)):
+                raise ValueError("adjoint arrays must be contiguous float64 tensors of the right size "
+                                 "on the solver's device")
         _check(load().sw_vjp_step(self.h, _ptr(stages), float(t), float(dt), _ptr(state_bar), _ptr(n_bar),
                                   _ptr(db_bar)), "sw_vjp_step")
 
@@ -485,7 +496,8 @@ class Solver:
             v = 1 | (mask << 1)
         _check(load().sw_profile(self.h, v), "sw_profile")
 
-    KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general", "element_tracer")
+    KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general", "element_tracer",
+               "element_tracer_final")
 
     def kernel_times(self):
         """{kernel class: (total ms, launches)} accumulated while profiling."""

@@ -319,7 +319,7 @@ struct sw_ctx {
   std::vector<void*> allocs;
   // kernel timing (sw_profile): events recorded around each launch group
   bool prof = false;
-  int prof_mask = 0x1F;      // kernel classes timed while profiling
+  int prof_mask = 0x7F;      // kernel classes timed while profiling
   struct Ev { int kind; int nlaunch; hipEvent_t a, b; };
   std::vector<Ev> ev;
   double prof_ms[8]{};
@@ -731,7 +731,7 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
     }
     if (fast_ok && tracer) {
       // tracer solve, C~ and tracer residual of the cells the fast kernel kept
-      sw_ctx::Scope sc(c, 5, 1);
+      sw_ctx::Scope sc(c, fmode == F_STAGE ? 5 : 6, 1);
       StageArgs tr = a;
       tr.need = c->d_need;
       HIPCHK(launch_trc(c->r, L.P, fmode, tr, L.nblk, c->s));
@@ -1968,13 +1968,13 @@ sw_status sw_get_workgroup(const sw_ctx* c, int32_t level, int32_t kernel, int32
 sw_status sw_profile(sw_ctx* c, int32_t on) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   c->prof = on != 0;
-  c->prof_mask = on > 1 ? (on >> 1) & 0x3F : 0x3F;
+  c->prof_mask = on > 1 ? (on >> 1) & 0x7F : 0x7F;
   return SW_OK;
 }
 
 sw_status sw_kernel_time(sw_ctx* c, int32_t kind, double* ms_total, int64_t* launches) {
   if (!c || !ms_total || !launches) return fail(SW_EINVAL, "NULL argument");
-  if (kind < 0 || kind > 5) return fail(SW_EINVAL, "kind must be 0..5");
+  if (kind < 0 || kind > 6) return fail(SW_EINVAL, "kind must be 0..6");
   for (auto& e : c->ev) {
     HIPCHK(hipEventSynchronize(e.b));
     float ms = 0.0f;

@@ -35,3 +35,32 @@ def test_multi_gpu_request_exits_with_a_message():
     assert p.returncode != 0
     assert "--gpus 1" in p.stderr
     assert p.stdout.strip() == ""
+
+
+def test_tracer_work_per_cell_counted_by_term():
+    S, r, m = 8, 3, 1.5
+    NP, NX, NT = 16, 10, 136
+    words = S * S + 3 * NP + 2 * NP + NP * m + 2 * NP
+    flops = S * S * (2 * 4 + 2 * NX + 2 * 4 * 3 + 2 * 4 * 2) + 2 * S * NT + NP ** 3 / 3 + 2 * NP * NP
+    b, f = bench.tracer_stage_work(S, r, m)
+    assert b == 8 * words and f == flops
+
+
+def test_roofline_bound_from_counters():
+    # a launch of 100 us moving 220 MB by the counters (0.275 of 8 TB/s) and
+    # issuing 33.3 M VALU instructions (0.54 of 1,024 SIMDs x 2.4 GHz / 4)
+    c = {"bytes_per_launch": 220e6, "valu_insts_per_launch": 33.3e6}
+    roof = bench.roofline(207e6, 2.0e9, 100e-6, c, "k")
+    assert roof["bound"] == "alu" and roof["unit"] == "TFLOP/s" and roof["bound_from"] == "counters"
+    assert abs(roof["valu_issue_frac"] - 33.3e6 * 4 / (1024 * 2.4e9 * 100e-6)) < 1e-4
+    assert abs(roof["frac"] - 20.0 / 78.6) < 1e-4
+    # HBM-busy counters give an HBM bound at the algorithmic rate
+    roof = bench.roofline(207e6, 2.0e9, 100e-6, {"bytes_per_launch": 700e6, "valu_insts_per_launch": 1e6}, "k")
+    assert roof["bound"] == "hbm" and abs(roof["frac"] - 2070.0 / 8000.0) < 1e-4
+    # without counters the larger algorithmic fraction decides, and says so
+    roof = bench.roofline(207e6, 2.0e9, 100e-6, None, "k")
+    assert roof["bound"] == "hbm" and roof["traffic"] is None and "no counter" in roof["bound_from"]
+
+
+def test_lanes_per_cell():
+    assert [bench.lanes_for(S) for S in (3, 5, 8, 9, 16, 17, 32)] == [4, 8, 8, 16, 16, 32, 32]
