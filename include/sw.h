@@ -106,6 +106,12 @@ typedef struct {
   int32_t tracer;            /* 0 or 1 passive tracer                              */
   int32_t adapt_degree;      /* 1: degree coarsening on, 0: always degree r        */
   double tide_amp, tide_period, tide_phase, tide_c_in;   /* SW_BC_ELEV data         */
+  /* tracer numerical diffusion (eq:numdiff): R_i gets - int nu_K h grad c .   */
+  /* grad psi_i with nu_K = tracer_diff |K| tracer_strain / r^2, the constant C */
+  /* and a characteristic strain rate S (1/s) of the resolved flow; and a     */
+  /* first-order decay, the reaction phi(c) = -tracer_decay c of eq:shw        */
+  /* (1/s), taken explicitly: R_i gets - tracer_decay int h c psi_i.  Zero: off */
+  double tracer_diff, tracer_strain, tracer_decay;
 } sw_params;
 
 typedef struct {

@@ -67,6 +67,13 @@ ambiguous or garbled (each one is also listed in the design notes):
   * Tracer in a dry cell keeps its start-of-step value.  A cell counts as dry
     when Hbar <= 1e-12 eps |K|: zero up to the round-off water that the dry
     lift of eq:initial_guess and the scalar solve of Hbar = 0 can leave.
+  * Tracer numerical diffusion (eq:numdiff) is the volume term as printed,
+    - int nu h grad c . grad psi_i with the plain depth, on the sample rule,
+    with nu_K = C |K| r^-2 S; the characteristic strain rate S of the
+    resolved flow, which the paper does not define, is a given constant of
+    the run.  A first-order decay, the reaction phi(c) = -kappa c of eq:shw,
+    enters R as - kappa int h c psi_i (explicit, as eq:imex_shw takes the
+    reactions).
 """
 from __future__ import annotations
 
@@ -330,6 +337,12 @@ class Params:
     cfl: float = 0.2
     cfl_mode: int = 0            # 0: dt = cfl*min J/(lam l); 1: dt = cfl*min w1 J/(lam l)
     tracer: bool = False
+    # tracer numerical diffusion (eq:numdiff): nu_K = C |K| r^-2 S with the
+    # constant C and a characteristic strain rate S of the resolved flow (1/s)
+    tracer_diff: float = 0.0
+    tracer_strain: float = 0.0
+    # first-order decay of the tracer, the reaction phi(c) = -kappa c of eq:shw (1/s)
+    tracer_decay: float = 0.0
     tide: tuple = (0.0, 1.0, 0.0, 0.0)   # amplitude, period, phase, inflow tracer
     adapt_degree: bool = True
 
@@ -568,8 +581,9 @@ class Oracle:
     def residual(self, state, t, dbed=None, nman=None, friction=True):
         """Weak residuals F (eq:mass_rhs), G = (Gx, Gy) (eq:discharge_rhs plus the
         explicit friction L of eq:discharge_rhs_implicit; without it when
-        friction=False) and R (eq:r_concentration), for every degree-r test
-        function, before any mass solve.
+        friction=False) and R (eq:r_concentration, plus the numerical
+        diffusion of eq:numdiff and the decay source -kappa int h c psi_i when
+        they are set), for every degree-r test function, before any mass solve.
 
         Also returns the positivity time-step bound min over face nodes and
         face sides of w * J_K / (lambda l_Gamma) (Prop. 3.2, eq:deltat_fe),
@@ -609,6 +623,14 @@ class Oracle:
                               - (W * g * h * zy) @ Bv - fr * ((W * gam * qyq) @ Bv))
             if p.tracer:
                 R = R.index_add(0, idx, (W * cq * qxq) @ Bx + (W * cq * qyq) @ By)
+                nu = p.tracer_diff * lv.dx ** 2 * p.tracer_strain / p.r ** 2
+                if nu != 0.0:
+                    # eq:numdiff: - int nu h grad c . grad psi_i
+                    cx, cy = (C @ lv.Bx.T) / lv.dx, (C @ lv.By.T) / lv.dx
+                    R = R.index_add(0, idx, -((W * nu * h * cx) @ Bx + (W * nu * h * cy) @ By))
+                if p.tracer_decay != 0.0:
+                    # the reaction source int h phi(c) psi_i with phi(c) = -kappa c
+                    R = R.index_add(0, idx, -((W * p.tracer_decay * h * cq) @ Bv))
         dtb = torch.tensor(float("inf"), dtype=DT)
         # ---- interior faces ----
         for fg in self.face_groups:

@@ -44,7 +44,9 @@ class SwParams(ctypes.Structure):
                 ("eps", ctypes.c_double), ("h_lim", ctypes.c_double), ("eps0", ctypes.c_double),
                 ("newton_max", ctypes.c_int32), ("cfl", ctypes.c_double), ("cfl_mode", ctypes.c_int32),
                 ("tracer", ctypes.c_int32), ("adapt_degree", ctypes.c_int32), ("tide_amp", ctypes.c_double),
-                ("tide_period", ctypes.c_double), ("tide_phase", ctypes.c_double), ("tide_c_in", ctypes.c_double)]
+                ("tide_period", ctypes.c_double), ("tide_phase", ctypes.c_double), ("tide_c_in", ctypes.c_double),
+                ("tracer_diff", ctypes.c_double), ("tracer_strain", ctypes.c_double),
+                ("tracer_decay", ctypes.c_double)]
 
 
 class SwDiag(ctypes.Structure):
@@ -155,6 +157,9 @@ def make_params(pd):
     p.adapt_degree = int(bool(pd.get("adapt_degree", True)))
     tide = tuple(pd.get("tide", (0.0, 1.0, 0.0, 0.0)))
     p.tide_amp, p.tide_period, p.tide_phase, p.tide_c_in = (float(v) for v in tide)
+    p.tracer_diff = float(pd.get("tracer_diff", 0.0))
+    p.tracer_strain = float(pd.get("tracer_strain", 0.0))
+    p.tracer_decay = float(pd.get("tracer_decay", 0.0))
     return p
 
 

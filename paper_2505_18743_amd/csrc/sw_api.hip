@@ -588,6 +588,8 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.eps0 = c->p.eps0;
   a.newton_max = c->p.newton_max;
   a.tracer = c->p.tracer ? 1 : 0;
+  a.tnu = c->p.tracer ? c->p.tracer_diff * c->p.tracer_strain / (double)(c->r * c->r) : 0.0;
+  a.tkap = c->p.tracer ? c->p.tracer_decay : 0.0;
   a.fric = 1;
   a.adapt = c->p.adapt_degree ? 1 : 0;
   // contiguous cell ranges per XCD on single-level meshes; on quadtrees the
@@ -855,17 +857,21 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   if (!(p->eps > 0.0)) return fail(SW_EINVAL, "eps must be > 0");
   if (p->newton_max < 1 || p->newton_max > 1000) return fail(SW_EINVAL, "newton_max out of range");
   if (p->n_levels < 1 || p->n_levels > 8) return fail(SW_EINVAL, "n_levels must be 1..8");
+  if (!(p->tracer_diff >= 0.0 && p->tracer_diff < 1e300) || !(p->tracer_strain >= 0.0 && p->tracer_strain < 1e300) ||
+      !(p->tracer_decay >= 0.0 && p->tracer_decay < 1e300))
+    return fail(SW_EINVAL, "tracer_diff, tracer_strain and tracer_decay must be finite and >= 0");
   for (int m = 0; m < n_members; ++m) {
     const sw_params& q = params[m];
     bool same = q.r == p->r && q.rule == p->rule && q.rk == p->rk && q.n_levels == p->n_levels && q.g == p->g &&
                 q.eps == p->eps && q.h_lim == p->h_lim && q.eps0 == p->eps0 && q.newton_max == p->newton_max &&
                 q.cfl_mode == p->cfl_mode && (q.tracer != 0) == (p->tracer != 0) &&
-                (q.adapt_degree != 0) == (p->adapt_degree != 0);
+                (q.adapt_degree != 0) == (p->adapt_degree != 0) && q.tracer_diff == p->tracer_diff &&
+                q.tracer_strain == p->tracer_strain && q.tracer_decay == p->tracer_decay;
     for (int L = 0; L < p->n_levels; ++L) same = same && q.S[L] == p->S[L];
     if (!same)
       return fail(SW_EINVAL, "member " + std::to_string(m) +
                                  ": members of one batch must share r, rule, rk, S, g, eps, h_lim, eps0, newton_max, "
-                                 "cfl_mode, tracer and adapt_degree");
+                                 "cfl_mode, tracer, adapt_degree and the tracer diffusion and decay");
     const sw_mesh_desc& md = meshes[m];
     const bool elev = md.bc[0] == SW_BC_ELEV || md.bc[1] == SW_BC_ELEV || md.bc[2] == SW_BC_ELEV ||
                       md.bc[3] == SW_BC_ELEV;

@@ -82,6 +82,8 @@ struct StageArgs {
   int nterm;             // number of stored residuals combined
   double a[4];           // combination weights a_{l,m} or b_m
   double g, eps, hlim, eps0;
+  double tnu;            // tracer numerical diffusion nu_K / |K| = C S / r^2 (eq:numdiff), 0: off
+  double tkap;           // tracer decay rate kappa (source -kappa h c), 0: off
   int newton_max, tracer, fric, adapt;
   int xmap;              // 1: fast kernels give each XCD one contiguous range of cells
 };

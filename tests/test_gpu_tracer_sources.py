@@ -1,0 +1,107 @@
+"""GPU: the tracer's numerical diffusion (eq:numdiff, nu_K = C |K| S / r^2)
+and first-order decay source (the reaction h phi(c), phi = -kappa c, of
+eq:shw) against the oracle: the tracer residual of one evaluation on the
+hanging quadtree mesh (r = 1, 2, 3), 20 coupled steps (SSP3 and IMEX), and
+further tracers, each with its own diffusion and decay, carried over one
+recorded flow by contexts of their own (sw_tracer_step): several tracers
+on one flow, each equal to its coupled run bit for bit and to the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from test_gpu_parity import TOL_RHS, TOL_STEP, compare_states, cpu, gpu_from_oracle, hanging_case, rel
+from test_gpu_tracer_replay import fixed_dt, record, replay
+
+pytestmark = pytest.mark.gpu
+
+SRC = dict(tracer_diff=0.33, tracer_strain=0.004, tracer_decay=2e-3)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def with_sources(o, **src):
+    for k, v in src.items():
+        setattr(o.p, k, v)
+    return o
+
+
+@pytest.mark.parametrize("r,S", [(1, (8, 4)), (2, (16, 8)), (3, (16, 8, 5))])
+def test_apply_operator_tracer_sources(r, S):
+    say(f"case: tracer residual with diffusion and decay, hanging mesh r={r} S={S}")
+    o, b = hanging_case(r, S)
+    with_sources(o, **SRC)
+    s = gpu_from_oracle(o, b)
+    rng = np.random.default_rng(30 + r)
+    st = o.get_state()
+    st = [st[0], rng.uniform(-0.5, 0.5, st[0].shape), rng.uniform(-0.5, 0.5, st[0].shape),
+          st[3] + 0.2 * rng.uniform(-1, 1, st[0].shape)]
+    F, Gx, Gy, R, _ = o.apply_operator(st, 700.0)
+    g = s.apply_operator(st[0], st[1], st[2], st[3], 700.0)
+    s.sync()
+    K = o.m.K
+    # the sources are a sizeable part of R
+    o0, _ = hanging_case(r, S)
+    R0 = o0.apply_operator(st, 700.0)[3]
+    assert np.abs(R - R0).max() > 1e-3 * np.abs(R).max()
+    for name, gg, rr in (("F", g[0], F), ("Gx", g[1], Gx), ("Gy", g[2], Gy), ("R", g[3], R)):
+        e = rel(cpu(gg, K), rr)
+        say(f"  {name} rel err {e:.3e}")
+        assert e < TOL_RHS, (name, e)
+    s.close()
+
+
+@pytest.mark.parametrize("rk", ["ssp3", "imex"])
+def test_steps_tracer_sources(rk):
+    say(f"case: 20 {rk} steps, hanging mesh + tide + tracer with diffusion and decay")
+    o, b = hanging_case(2, (16, 8))
+    o.p.rk = rk
+    with_sources(o, **SRC)
+    s = gpu_from_oracle(o, b)
+    s.set_state(*o.get_state())
+    for _ in range(20):
+        o.step()
+        s.step()
+    s.sync()
+    compare_states(o, s, TOL_STEP, "20 steps")
+    s.close()
+
+
+def test_several_tracers_over_one_recorded_flow():
+    say("case: one flow recorded (tracer without sources), two more tracers with their own sources replayed")
+    o, b = hanging_case(2, (16, 8))
+    st0 = o.get_state()
+    rec = gpu_from_oracle(o, b)
+    dt = fixed_dt(rec, st0)
+    n = 12
+    stages, end, _ = record(rec, st0, dt, n)
+    dof = o.dof_coords()
+    tracers = [(dict(tracer_diff=0.33, tracer_strain=0.004, tracer_decay=0.0),
+                np.where(dof[..., 0] < 1300.0, 1.0, 0.25) + 0.1 * np.sin(dof[..., 1] / 200.0)),
+               (dict(tracer_diff=0.0, tracer_strain=0.0, tracer_decay=5e-3), 0.5 + 0.3 * np.cos(dof[..., 0] / 300.0))]
+    K = o.m.K
+    for src, c in tracers:
+        oi, _ = hanging_case(2, (16, 8))
+        with_sources(oi, **src)
+        rep = gpu_from_oracle(oi, b)
+        st = [st0[0], st0[1], st0[2], c]
+        got = replay(rep, st, stages, end, dt)
+        # its coupled run on the GPU, bit for bit
+        rep.set_state(*st)
+        rep.set_time(0.0)
+        for _ in range(n):
+            rep.step(dt)
+        rep.sync()
+        ref = rep.get_state()
+        assert torch.equal(got[3], ref[3]), (src, float((got[3] - ref[3]).abs().max()))
+        # and the oracle's coupled run with the same sources
+        oi.state[3] = torch.as_tensor(c)
+        for _ in range(n):
+            oi.step(dt)
+        e = rel(cpu(got[3], K), oi.adapted_state()[3])
+        say(f"  sources {src}: replayed tracer vs oracle rel err {e:.3e}")
+        assert e < TOL_STEP
+        rep.close()
+    rec.close()
