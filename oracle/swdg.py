@@ -345,6 +345,11 @@ class Params:
     tracer_decay: float = 0.0
     tide: tuple = (0.0, 1.0, 0.0, 0.0)   # amplitude, period, phase, inflow tracer
     adapt_degree: bool = True
+    # "subgrid": the S x S sample rule serves every element integral;
+    # "paper": the rules of Table 1 (volume terms GL (floor(3r/2)+1)^2 with
+    # samples of their own, faces and the continuity / tracer mass GLL
+    # (r+2)^2, discharge mass GL (r+1)^2); S must then be r + 2 with rule "gll"
+    quadrature: str = "subgrid"
 
 
 @dataclass
@@ -360,6 +365,13 @@ class _Level:
     w1: float                    # endpoint weight of the 1-D rule
     zb: torch.Tensor = None      # [K_L, S*S] bathymetry depth samples
     pos: dict = field(default_factory=dict)
+
+
+class _Vol:
+    """Attribute view of a level's volume-rule tables (the paper's quadrature)."""
+
+    def __init__(self, d):
+        self.W, self.Bv, self.Bx, self.By = d["W"], d["Bv"], d["Bx"], d["By"]
 
 
 def _pos(x):
@@ -422,6 +434,18 @@ class Oracle:
                         torch.as_tensor(v), torch.as_tensor(gx), torch.as_tensor(gy), float(wh[0]))
             lv.zb = torch.zeros(len(idx), S * S, dtype=DT)
             lv.xh = xh
+            lv.vol = None
+            if p.quadrature == "paper":
+                if p.rule != "gll" or S != r + 2:
+                    raise ValueError("the paper's quadrature takes the GLL rule with S = r + 2 (Table 1)")
+                nv = (3 * r) // 2 + 1
+                xv, wv = gl_rule(nv)
+                vv, gxv, gyv = tensor_basis(r, np.tile(xv, nv), np.repeat(xv, nv))
+                lv.vol = dict(n=nv, xh=xv, W=torch.as_tensor(np.outer(wv, wv).ravel() * dx * dx),
+                              Bv=torch.as_tensor(vv), Bx=torch.as_tensor(gxv), By=torch.as_tensor(gyv),
+                              zb=torch.zeros(len(idx), nv * nv, dtype=DT))
+            elif p.quadrature != "subgrid":
+                raise ValueError(f"unknown quadrature {p.quadrature!r}")
             self.cell_level_pos[lv.idx] = torch.arange(len(idx))
             self.levels.append(lv)
         self.level_of = {lv.L: lv for lv in self.levels}
@@ -441,16 +465,19 @@ class Oracle:
 
     # -- geometry ----------------------------------------------------------
     def node_coords(self):
-        """Sample-node coordinates, cell by cell, nodes q = b*S + a: x = x0 + (i + xh_a) dx."""
+        """Sample-node coordinates, cell by cell, nodes q = b*S + a: x = x0 + (i + xh_a) dx.
+        With the paper's quadrature the volume rule's nodes of every cell follow,
+        cell by cell, in the same layout."""
         out = []
         m = self.m
-        for k in range(m.K):
-            lv = self.level_of[int(m.level[k])]
-            xh = lv.xh
-            S = lv.S
-            X = m.x0 + (m.ii[k] + np.tile(xh, S)) * lv.dx
-            Y = m.y0 + (m.jj[k] + np.repeat(xh, S)) * lv.dx
-            out.append(np.stack([X, Y], 1))
+        sets = [("xh", "S")] + ([("vol", None)] if self.p.quadrature == "paper" else [])
+        for which, _ in sets:
+            for k in range(m.K):
+                lv = self.level_of[int(m.level[k])]
+                xh, S = (lv.xh, lv.S) if which == "xh" else (lv.vol["xh"], lv.vol["n"])
+                X = m.x0 + (m.ii[k] + np.tile(xh, S)) * lv.dx
+                Y = m.y0 + (m.jj[k] + np.repeat(xh, S)) * lv.dx
+                out.append(np.stack([X, Y], 1))
         return np.concatenate(out, 0) if out else np.zeros((0, 2))
 
     def dof_coords(self):
@@ -472,11 +499,22 @@ class Oracle:
             S = self.level_of[int(self.m.level[k])].S
             per_cell.append((off, S))
             off += S * S
+        voff = off
+        if self.p.quadrature == "paper":
+            for k in range(self.m.K):
+                n = self.level_of[int(self.m.level[k])].vol["n"]
+                per_cell[k] = per_cell[k] + (off, n)
+                off += n * n
         if off != b.numel():
             raise ValueError("bathymetry size mismatch")
         for lv in self.levels:
             rows = [b[per_cell[k][0]: per_cell[k][0] + lv.S ** 2] for k in lv.idx.tolist()]
             lv.zb = -torch.stack(rows, 0) if rows else torch.zeros(0, lv.S ** 2, dtype=DT)
+            if lv.vol is not None:
+                n = lv.vol["n"]
+                rows = [b[per_cell[k][2]: per_cell[k][2] + n * n] for k in lv.idx.tolist()]
+                lv.vol["zb"] = -torch.stack(rows, 0) if rows else torch.zeros(0, n * n, dtype=DT)
+        del voff
 
     def set_manning(self, n_cell):
         self.nman = torch.as_tensor(np.asarray(n_cell, dtype=np.float64)).clone()
@@ -497,6 +535,11 @@ class Oracle:
         """Depth samples of a level with the per-cell offset: b -> b + db, zb -> zb - db."""
         db = self.dbed if dbed is None else dbed
         return lv.zb - db[lv.idx][:, None]
+
+    def zb_vol_eff(self, lv, dbed=None):
+        """The same at the nodes of the paper's volume rule."""
+        db = self.dbed if dbed is None else dbed
+        return lv.vol["zb"] - db[lv.idx][:, None]
 
     def init_lake_at_rest(self, eta_nodal):
         """Definition 3.1: zeta_j = given value if some rule node is wet, else -max_q zb."""
@@ -603,16 +646,19 @@ class Oracle:
             if len(idx) == 0:
                 continue
             Z, QX, QY, C = zeta[idx], qx[idx], qy[idx], c[idx]
-            zq = Z @ lv.Bv.T
-            zx = (Z @ lv.Bx.T) / lv.dx
-            zy = (Z @ lv.By.T) / lv.dx
-            qxq, qyq, cq = QX @ lv.Bv.T, QY @ lv.Bv.T, C @ lv.Bv.T
-            h = _pos(zq + self.zb_eff(lv, dbed))
+            # the volume rule: the sample rule, or Table 1's GL rule
+            vr = lv if lv.vol is None else _Vol(lv.vol)
+            zq = Z @ vr.Bv.T
+            zx = (Z @ vr.Bx.T) / lv.dx
+            zy = (Z @ vr.By.T) / lv.dx
+            qxq, qyq, cq = QX @ vr.Bv.T, QY @ vr.Bv.T, C @ vr.Bv.T
+            zbv = self.zb_eff(lv, dbed) if lv.vol is None else self.zb_vol_eff(lv, dbed)
+            h = _pos(zq + zbv)
             ih = _inv_des(h, p.eps)
             ux, uy = qxq * ih, qyq * ih
             gam = g * nman[idx][:, None] ** 2 * _safe_norm(qxq, qyq) * ih ** (7.0 / 3.0)
-            W = lv.W
-            Bx, By, Bv = lv.Bx / lv.dx, lv.By / lv.dx, lv.Bv
+            W = vr.W
+            Bx, By, Bv = vr.Bx / lv.dx, vr.By / lv.dx, vr.Bv
             # F_i += int q . grad psi_i
             F = F.index_add(0, idx, (W * qxq) @ Bx + (W * qyq) @ By)
             # G_i,k += int q_k (u . grad psi_i) - g h d_k zeta psi_i - gamma q_k psi_i
@@ -626,7 +672,7 @@ class Oracle:
                 nu = p.tracer_diff * lv.dx ** 2 * p.tracer_strain / p.r ** 2
                 if nu != 0.0:
                     # eq:numdiff: - int nu h grad c . grad psi_i
-                    cx, cy = (C @ lv.Bx.T) / lv.dx, (C @ lv.By.T) / lv.dx
+                    cx, cy = (C @ vr.Bx.T) / lv.dx, (C @ vr.By.T) / lv.dx
                     R = R.index_add(0, idx, -((W * nu * h * cx) @ Bx + (W * nu * h * cy) @ By))
                 if p.tracer_decay != 0.0:
                     # the reaction source int h phi(c) psi_i with phi(c) = -kappa c
@@ -1054,16 +1100,20 @@ class Oracle:
             idx = lv.idx
             if len(idx) == 0:
                 continue
-            zq = zeta[idx] @ lv.Bv.T
-            qxq, qyq = qx[idx] @ lv.Bv.T, qy[idx] @ lv.Bv.T
-            h = _pos(zq + self.zb_eff(lv, None))
+            # the volume rule (with the paper's quadrature the friction matrix
+            # takes it too: its depth needs bathymetry values at its nodes)
+            vr = lv if lv.vol is None else _Vol(lv.vol)
+            zq = zeta[idx] @ vr.Bv.T
+            qxq, qyq = qx[idx] @ vr.Bv.T, qy[idx] @ vr.Bv.T
+            zbv = self.zb_eff(lv, None) if lv.vol is None else self.zb_vol_eff(lv, None)
+            h = _pos(zq + zbv)
             ih = _inv_des(h, p.eps)
             gn2q = p.g * nman[idx][:, None] ** 2 * _safe_norm(qxq, qyq)
             gam_des = gn2q * ih ** (7.0 / 3.0)                     # gamma(|q|, h_des)
             live = (h > 0) & (gn2q > 0)
             hs = torch.where(live, h, torch.ones_like(h))
             gam_h = torch.where(live, gn2q / hs ** (7.0 / 3.0), torch.zeros_like(h))   # gamma(|q|, h)
-            W, Bv = lv.W, lv.Bv
+            W, Bv = vr.W, vr.Bv
             Lx[idx] = -((W * gam_des * qxq) @ Bv)
             Ly[idx] = -((W * gam_des * qyq) @ Bv)
             Gam[idx] = torch.einsum("kq,qi,qj->kij", W * gam_h, Bv, Bv)
