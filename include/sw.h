@@ -70,6 +70,17 @@ enum { SW_BC_WALL = 0,      /* ghost mirrors the normal discharge               
 enum { SW_RULE_EQ = 0,      /* closed equispaced (composite trapezoid) rule         */
        SW_RULE_GLL = 1 };   /* Gauss-Legendre-Lobatto rule                         */
 
+enum { SW_QUAD_SUBGRID = 0, /* the S x S sample rule serves every element integral  */
+       SW_QUAD_PAPER = 1 }; /* Table 1: volume terms (F, G, R, the friction L and  */
+                            /* its matrix) on Gauss-Legendre (floor(3r/2)+1)^2     */
+                            /* nodes with bathymetry samples of their own; faces, */
+                            /* the wet/dry rule and the continuity and tracer     */
+                            /* masses on the GLL (r+2)^2 sample rule; discharge   */
+                            /* mass exact (GL (r+1)^2).  Needs SW_RULE_GLL with   */
+                            /* S = r + 2 on every level.  Every cell then takes   */
+                            /* the general element kernel; sw_vjp_operator and    */
+                            /* sw_vjp_step reject such a context.                 */
+
 enum { SW_RK_FE = 0, SW_RK_SSP3 = 1, SW_RK_RK32 = 2, SW_RK_RK44 = 3,  /* Appendix A */
        SW_RK_IMEX = 4 };    /* Sec. 3.1 IMEX pair of Appendix A: the explicit     */
                             /* RK32 tableau for everything but the Manning        */
@@ -112,6 +123,7 @@ typedef struct {
   /* first-order decay, the reaction phi(c) = -tracer_decay c of eq:shw        */
   /* (1/s), taken explicitly: R_i gets - tracer_decay int h c psi_i.  Zero: off */
   double tracer_diff, tracer_strain, tracer_decay;
+  int32_t quadrature;        /* SW_QUAD_*                                          */
 } sw_params;
 
 typedef struct {
@@ -179,15 +191,20 @@ sw_status sw_locate_points(const sw_ctx *c, int32_t member, int32_t n, const dou
 sw_status sw_boundary_nodes(const sw_ctx *c, int64_t *n_nodes, double *xy_host, int32_t *member_host);
 sw_status sw_set_boundary_state(sw_ctx *c, const double *ghost_dev);
 
-/* Sizes: cells, sample nodes (sum of S_L^2), nodal values per field. */
+/* Sizes: cells, bathymetry nodes (sum over cells of S_L^2, plus, with
+ * SW_QUAD_PAPER, (floor(3r/2)+1)^2 volume-rule nodes per cell), nodal values
+ * per field. */
 sw_status sw_counts(const sw_ctx *c, int64_t *n_cells, int64_t *n_vol_nodes, int64_t *n_dofs);
 
-/* Host outputs: sample-node coordinates [n_vol_nodes][2] and basis support
- * point coordinates [n_dofs][2].  Synchronises. */
+/* Host outputs: bathymetry-node coordinates [n_vol_nodes][2] and basis
+ * support point coordinates [n_dofs][2].  The sample nodes of every cell come
+ * first (cells in context order, node q = b S + a at (x_a, y_b)); with
+ * SW_QUAD_PAPER the volume-rule nodes of every cell follow in the same
+ * layout.  Synchronises. */
 sw_status sw_node_coords(const sw_ctx *c, double *xy_host);
 sw_status sw_dof_coords(const sw_ctx *c, double *xy_host);
 
-/* Bed ELEVATION b at the sample nodes (device, [n_vol_nodes]).  The library
+/* Bed ELEVATION b at the nodes of sw_node_coords (device, [n_vol_nodes]).  The library
  * stores the bathymetry depth z_b = -(b + db_K) of Sec. 2 (db: bed offset). */
 sw_status sw_set_bathymetry(sw_ctx *c, const double *b_dev);
 /* Per-cell Manning coefficient n_K (eq:manning), device [n_cells]. */

@@ -17,6 +17,7 @@ LIBPATH = os.path.join(HERE, "libswdg.so")
 BC = {"wall": 0, "elev": 1, "open": 2, "periodic": 3, "state": 4, "discharge": 5}
 RULE = {"eq": 0, "gll": 1}
 RK = {"fe": 0, "ssp3": 1, "rk32": 2, "rk44": 3, "imex": 4}
+QUADRATURE = {"subgrid": 0, "paper": 1}
 
 EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_cell_map", "sw_counts",
            "sw_node_coords", "sw_dof_coords", "sw_set_bathymetry", "sw_set_manning", "sw_set_bed_offset",
@@ -46,7 +47,7 @@ class SwParams(ctypes.Structure):
                 ("tracer", ctypes.c_int32), ("adapt_degree", ctypes.c_int32), ("tide_amp", ctypes.c_double),
                 ("tide_period", ctypes.c_double), ("tide_phase", ctypes.c_double), ("tide_c_in", ctypes.c_double),
                 ("tracer_diff", ctypes.c_double), ("tracer_strain", ctypes.c_double),
-                ("tracer_decay", ctypes.c_double)]
+                ("tracer_decay", ctypes.c_double), ("quadrature", ctypes.c_int32)]
 
 
 class SwDiag(ctypes.Structure):
@@ -160,6 +161,7 @@ def make_params(pd):
     p.tracer_diff = float(pd.get("tracer_diff", 0.0))
     p.tracer_strain = float(pd.get("tracer_strain", 0.0))
     p.tracer_decay = float(pd.get("tracer_decay", 0.0))
+    p.quadrature = QUADRATURE[pd.get("quadrature", "subgrid")]
     return p
 
 

@@ -263,6 +263,12 @@ struct LevelH {
   std::vector<double> xh, wh;
   double* d_tab = nullptr;
   LevelTabs tabs{};
+  // volume terms on Table 1's Gauss-Legendre rule (SW_QUAD_PAPER): its nodes,
+  // weights and tables, and the offset of the level's volume-rule samples
+  std::vector<double> xv, wv;
+  double* d_vtab = nullptr;
+  LevelTabs vtabs{};
+  size_t voff = 0;
 };
 
 }  // namespace
@@ -272,7 +278,9 @@ struct sw_ctx {
   hipStream_t s = nullptr;
   sw_params p{};
   int r = 1, N1 = 2, NP = 4, K = 0, F = 0, ns = 3, M = 1;
-  int64_t nvol = 0;
+  int64_t nvol = 0;          // sample nodes (sum over cells of S^2)
+  int nv = 0;                 // SW_QUAD_PAPER: volume-rule nodes per direction (0: the sample rule)
+  int64_t nvv = 0;            // volume-rule nodes (K nv^2), stored after the sample nodes
   // members: coarse-grid origin and cell size; per cell: member, index in the
   // member's description, level, integer position, size
   std::vector<double> mx0, my0, mdx0;
@@ -537,6 +545,36 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.mq = L.d_tab + o_mqf;
   L.tabs.S = S;
   L.w1 = L.wh[0];
+  L.vtabs = L.tabs;
+  if (c->nv > 0) {
+    // the volume terms' Gauss-Legendre rule (Table 1): weights, basis values
+    // and derivatives at its nodes, and their weighted forms; the mass-matrix
+    // entries stay the sample rule's (unused with this rule)
+    const int nv = c->nv;
+    gl(nv, L.xv, L.wv);
+    const size_t v_w = 0, v_l = nv, v_d = v_l + (size_t)nv * N1, v_wl = v_d + (size_t)nv * N1,
+                 v_wd = v_wl + (size_t)nv * N1, vtotal = v_wd + (size_t)nv * N1;
+    std::vector<double> vt(vtotal, 0.0);
+    for (int a = 0; a < nv; ++a) {
+      vt[v_w + a] = L.wv[a];
+      for (int k = 0; k < N1; ++k) {
+        vt[v_l + a * N1 + k] = lag(xi, k, L.xv[a]);
+        vt[v_d + a * N1 + k] = dlag(xi, k, L.xv[a]);
+        vt[v_wl + a * N1 + k] = L.wv[a] * lag(xi, k, L.xv[a]);
+        vt[v_wd + a * N1 + k] = L.wv[a] * dlag(xi, k, L.xv[a]);
+      }
+    }
+    st = c->alloc(&L.d_vtab, vtotal);
+    if (st != SW_OK) return st;
+    HIPCHK(hipMemcpy(L.d_vtab, vt.data(), vtotal * sizeof(double), hipMemcpyHostToDevice));
+    L.vtabs.w = L.d_vtab + v_w;
+    L.vtabs.l = L.d_vtab + v_l;
+    L.vtabs.d = L.d_vtab + v_d;
+    L.vtabs.wl = L.d_vtab + v_wl;
+    L.vtabs.wd = L.d_vtab + v_wd;
+    L.vtabs.fl = nullptr;
+    L.vtabs.S = nv;
+  }
   return SW_OK;
 }
 
@@ -552,6 +590,9 @@ StageArgs stage_args(sw_ctx* c, const LevelH& L) {
   a.ncell = L.ncell;
   a.K = c->K;
   a.zb = c->d_zb + L.off;
+  a.vol = c->nv > 0 ? 1 : 0;
+  a.tv = L.vtabs;
+  a.zbv = c->d_zb + L.voff;
   a.bvec = c->d_bvec;
   a.zmax = c->d_zmax;
   a.nman = c->d_nman;
@@ -706,9 +747,10 @@ sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
 // diagonal weight
 sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
                    int kind, const double* coeft = nullptr, double att = 0.0) {
-  // a tracer replay runs the general kernel on every cell
+  // a tracer replay, and the volume terms on a rule of their own, run the
+  // general kernel on every cell
   const bool tracer = c->p.tracer != 0;
-  const bool fast_ok = !(tracer && c->rp[0] != nullptr);
+  const bool fast_ok = !(tracer && c->rp[0] != nullptr) && c->nv == 0;
   if (fast_ok && tracer && fmode == F_FINAL) {
     // the final kernel updates the degree flags; the tracer kernel reads the step's own
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
@@ -774,6 +816,12 @@ sw_status rebake(sw_ctx* c) {
     hipLaunchKernelGGL(k_bathy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->s, c->d_braw, c->d_db, c->d_zb,
                        L.cell0, L.ncell, L.S, L.off);
     HIPCHK(hipGetLastError());
+    if (c->nv > 0) {   // the volume rule's depth samples
+      const size_t nvn = (size_t)L.ncell * c->nv * c->nv;
+      hipLaunchKernelGGL(k_bathy, dim3((unsigned)((nvn + 255) / 256)), dim3(256), 0, c->s, c->d_braw, c->d_db,
+                         c->d_zb, L.cell0, L.ncell, c->nv, L.voff);
+      HIPCHK(hipGetLastError());
+    }
   }
   for (auto& L : c->lv) {
     if (L.nface > 0) {
@@ -860,18 +908,28 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   if (!(p->tracer_diff >= 0.0 && p->tracer_diff < 1e300) || !(p->tracer_strain >= 0.0 && p->tracer_strain < 1e300) ||
       !(p->tracer_decay >= 0.0 && p->tracer_decay < 1e300))
     return fail(SW_EINVAL, "tracer_diff, tracer_strain and tracer_decay must be finite and >= 0");
+  if (p->quadrature != SW_QUAD_SUBGRID && p->quadrature != SW_QUAD_PAPER)
+    return fail(SW_EINVAL, "unknown quadrature");
+  if (p->quadrature == SW_QUAD_PAPER) {
+    // Table 1: faces and the continuity mass on GLL (r+2)^2
+    if (p->rule != SW_RULE_GLL) return fail(SW_EINVAL, "the paper's quadrature takes the GLL rule (Table 1)");
+    for (int L = 0; L < p->n_levels; ++L)
+      if (p->S[L] != p->r + 2) return fail(SW_EINVAL, "the paper's quadrature takes S = r + 2 on every level");
+  }
   for (int m = 0; m < n_members; ++m) {
     const sw_params& q = params[m];
     bool same = q.r == p->r && q.rule == p->rule && q.rk == p->rk && q.n_levels == p->n_levels && q.g == p->g &&
                 q.eps == p->eps && q.h_lim == p->h_lim && q.eps0 == p->eps0 && q.newton_max == p->newton_max &&
                 q.cfl_mode == p->cfl_mode && (q.tracer != 0) == (p->tracer != 0) &&
                 (q.adapt_degree != 0) == (p->adapt_degree != 0) && q.tracer_diff == p->tracer_diff &&
-                q.tracer_strain == p->tracer_strain && q.tracer_decay == p->tracer_decay;
+                q.tracer_strain == p->tracer_strain && q.tracer_decay == p->tracer_decay &&
+                q.quadrature == p->quadrature;
     for (int L = 0; L < p->n_levels; ++L) same = same && q.S[L] == p->S[L];
     if (!same)
       return fail(SW_EINVAL, "member " + std::to_string(m) +
                                  ": members of one batch must share r, rule, rk, S, g, eps, h_lim, eps0, newton_max, "
-                                 "cfl_mode, tracer, adapt_degree and the tracer diffusion and decay");
+                                 "cfl_mode, tracer, adapt_degree, the tracer diffusion and decay and the "
+                                 "quadrature");
     const sw_mesh_desc& md = meshes[m];
     const bool elev = md.bc[0] == SW_BC_ELEV || md.bc[1] == SW_BC_ELEV || md.bc[2] == SW_BC_ELEV ||
                       md.bc[3] == SW_BC_ELEV;
@@ -971,6 +1029,11 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
       off += (int64_t)L.ncell * L.S * L.S;
     }
     c->nvol = off;
+    // the volume rule of Table 1 has floor(3r/2)+1 Gauss-Legendre points per
+    // direction; its samples follow the sample nodes, cell by cell
+    c->nv = p->quadrature == SW_QUAD_PAPER ? (3 * p->r) / 2 + 1 : 0;
+    for (auto& L : c->lv) L.voff = (size_t)c->nvol + (size_t)L.cell0 * c->nv * c->nv;
+    c->nvv = (int64_t)K * c->nv * c->nv;
   }
   // faces: conforming (recorded from the W/S cell), hanging (from the fine cell),
   // boundary; A is the fine or equal side.  Faces join cells of one member only.
@@ -1089,8 +1152,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_meta, c->F);
     ALLOC(c->d_err, 1);
     ALLOC(c->d_cmem, K);
-    ALLOC(c->d_zb, (size_t)c->nvol);
-    ALLOC(c->d_braw, (size_t)c->nvol);
+    ALLOC(c->d_zb, (size_t)(c->nvol + c->nvv));
+    ALLOC(c->d_braw, (size_t)(c->nvol + c->nvv));
     ALLOC(c->d_db, K);
     ALLOC(c->d_bvec, KN);
     ALLOC(c->d_zmax, K);
@@ -1251,7 +1314,7 @@ void sw_destroy(sw_ctx* c) {
 sw_status sw_counts(const sw_ctx* c, int64_t* n_cells, int64_t* n_vol, int64_t* n_dofs) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (n_cells) *n_cells = c->K;
-  if (n_vol) *n_vol = c->nvol;
+  if (n_vol) *n_vol = c->nvol + c->nvv;
   if (n_dofs) *n_dofs = (int64_t)c->K * c->NP;
   return SW_OK;
 }
@@ -1268,6 +1331,15 @@ sw_status sw_node_coords(const sw_ctx* c, double* xy) {
           o[2 * (b * L.S + a) + 0] = x0 + (c->ci[k] + L.xh[a]) * dx;
           o[2 * (b * L.S + a) + 1] = y0 + (c->cj[k] + L.xh[b]) * dx;
         }
+      if (c->nv > 0) {
+        const int nv = c->nv;
+        double* ov = xy + 2 * (L.voff + (size_t)cl * nv * nv);
+        for (int b = 0; b < nv; ++b)
+          for (int a = 0; a < nv; ++a) {
+            ov[2 * (b * nv + a) + 0] = x0 + (c->ci[k] + L.xv[a]) * dx;
+            ov[2 * (b * nv + a) + 1] = y0 + (c->cj[k] + L.xv[b]) * dx;
+          }
+      }
     }
   }
   return SW_OK;
@@ -1369,8 +1441,8 @@ sw_status sw_set_bathymetry(sw_ctx* c, const double* b) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   sw_status st = check_ptr(b, "b");
   if (st != SW_OK) return st;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)((c->nvol + 255) / 256)), dim3(256), 0, c->s, b, c->d_braw,
-                     (size_t)c->nvol);
+  const int64_t nb = c->nvol + c->nvv;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, c->s, b, c->d_braw, (size_t)nb);
   HIPCHK(hipGetLastError());
   c->bathy_set = true;
   return rebake(c);
@@ -1759,6 +1831,7 @@ sw_status sw_vjp_operator(sw_ctx* c, const double* eta, const double* qx, const 
   if (!c) return fail(SW_EINVAL, "NULL context");
   if (!eta || !qx || !qy || !Fb || !Gxb || !Gyb || !eta_b || !qx_b || !qy_b || !n_bar || !db_bar)
     return fail(SW_EINVAL, "all arrays of sw_vjp_operator must be non-NULL");
+  if (c->nv > 0) return fail(SW_EINVAL, "the adjoint covers the sample-rule quadrature, not SW_QUAD_PAPER");
   sw_status st = need_inputs(c);
   if (st != SW_OK) return st;
   const unsigned nbk = (unsigned)((c->K + 255) / 256);
@@ -1789,6 +1862,7 @@ sw_status sw_vjp_step(sw_ctx* c, const double* stages, double t, double dt, doub
   if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_vjp_step needs the step's fixed dt > 0");
   if (c->p.tracer) return fail(SW_EINVAL, "the step adjoint covers runs without a tracer");
   if (c->imex) return fail(SW_EINVAL, "the step adjoint covers the explicit schemes, not IMEX");
+  if (c->nv > 0) return fail(SW_EINVAL, "the adjoint covers the sample-rule quadrature, not SW_QUAD_PAPER");
   if (c->stage_done != 0) return fail(SW_EINVAL, "sw_vjp_step cannot run inside an open step");
   sw_status st = need_inputs(c);
   if (st != SW_OK) return st;

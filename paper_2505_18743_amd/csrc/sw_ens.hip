@@ -70,7 +70,8 @@ std::vector<double> batch_key(const sw_params& p) {
   std::vector<double> k = {(double)p.r,   (double)p.rule, (double)p.rk,         (double)p.n_levels,
                            p.g,           p.eps,          p.h_lim,              p.eps0,
                            (double)p.newton_max, (double)p.cfl_mode, (double)(p.tracer != 0),
-                           (double)(p.adapt_degree != 0), p.tracer_diff, p.tracer_strain, p.tracer_decay};
+                           (double)(p.adapt_degree != 0), p.tracer_diff, p.tracer_strain, p.tracer_decay,
+                           (double)p.quadrature};
   for (int L = 0; L < 8; ++L) k.push_back(L < p.n_levels ? (double)p.S[L] : 0.0);
   return k;
 }

@@ -42,6 +42,11 @@ struct StageArgs {
   LevelTabs t;
   int cell0, ncell, K;
   const double* zb;      // level block of internal depth samples [ncell][S(a)][S(b)]
+  // volume terms on a rule of their own (Table 1's Gauss-Legendre rule): its
+  // tables and depth samples [ncell][nv(a)][nv(b)]; vol = 0: the sample rule
+  int vol;
+  LevelTabs tv;
+  const double* zbv;
   const double* bvec;    // [K][NP] all-wet B_i = sum W psi_i zb
   const double* zmax;    // [K]     max depth sample
   const double* nman;    // [K]

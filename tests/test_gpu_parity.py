@@ -52,7 +52,7 @@ def oracle_params(o):
     return dict(r=p.r, S=p.S, rule=p.rule, rk=p.rk, g=p.g, eps=p.eps, h_lim=p.h_lim, eps0=p.eps0,
                 newton_max=p.newton_max, cfl=p.cfl, cfl_mode=p.cfl_mode, tracer=p.tracer, tide=p.tide,
                 adapt_degree=p.adapt_degree, tracer_diff=p.tracer_diff, tracer_strain=p.tracer_strain,
-                tracer_decay=p.tracer_decay)
+                tracer_decay=p.tracer_decay, quadrature=p.quadrature)
 
 
 def mesh_dict(m):
