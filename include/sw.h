@@ -293,6 +293,69 @@ sw_status sw_step_record(sw_ctx *c, double dt, double *stages_dev, double *end_d
 sw_status sw_vjp_step(sw_ctx *c, const double *stages_dev, double t, double dt, double *state_bar,
                       double *n_bar, double *db_bar);
 
+/* ---- Dynamic h-adaptivity (Sec. 3.3 "Degree and h-adaptivity": refinement
+ * criteria; Sec. 3.4: conservative remap, eq:cons-remap, and the mass source
+ * Q^n of bathymetry re-sampling, eq:mass-loss) ---- */
+enum { SW_AMR_VORTICITY = 0,   /* eta_K = max |curl u| (Sec. 4.4), u = q / h_des    */
+                               /* (eq:velocity) by the chain rule with the depth   */
+                               /* gradient grad zeta at wet nodes, 0 at dry ones   */
+       SW_AMR_TRACER_GRAD = 1 };/* eta_K = max |grad c| (Sec. 5)                    */
+
+typedef struct {
+  int32_t indicator;         /* SW_AMR_*                                           */
+  double theta_r, theta_c;   /* refine if eta_K > theta_r eta_max, coarsen if      */
+                             /* eta_K < theta_c eta_max (eta_max over the mesh)    */
+  int32_t n_max;             /* finest level n_K = level + 1 <= n_max (<= n_levels)*/
+  double h_min;              /* no refinement of cells of size <= h_min (0: none) */
+} sw_amr_params;
+
+typedef struct {
+  int64_t n_cells_old, n_cells_new;
+  int64_t n_refined;         /* cells split (flagged or for the 2:1 balance)       */
+  int64_t n_coarsened;       /* groups of four siblings merged                     */
+  double eta_max;
+  double mass_old, mass_new; /* sum_K int h before and after (sample rule)         */
+  double q_bathy;            /* Q^n of eq:mass-loss: sum_K int z_b l over the new  */
+                             /* cells minus the same over the old cells, l the     */
+                             /* land-sea mask of the state on each mesh           */
+} sw_amr_stats;
+
+/* Bathymetry raster: bed ELEVATION b_dev[j][i] (device, nx x ny, nx, ny >= 2)
+ * at (x0 + i dx, y0 + j dy).  The library keeps a copy and samples it by
+ * bilinear interpolation (clamped to the raster's edge outside it) at every
+ * node of sw_node_coords, now and at the new cells of every sw_remesh; this
+ * replaces sw_set_bathymetry (the bed offsets still apply). */
+sw_status sw_set_bed_grid(sw_ctx *c, int32_t nx, int32_t ny, double x0, double y0, double dx, double dy,
+                          const double *b_dev);
+/* eta_K of every cell (device [n_cells]) at the state the next step starts
+ * from, evaluated at the nodes of the volume integrals (the S x S sample
+ * rule, or Table 1's Gauss-Legendre rule with SW_QUAD_PAPER). */
+sw_status sw_amr_indicator(sw_ctx *c, int32_t indicator, double *eta_dev);
+/* One remesh of a single-member context, between steps.  From the indicator
+ * at the state the next step starts from: refine K if eta_K > theta_r eta_max,
+ * n_K < n_max and its size exceeds h_min; merge four sibling leaves if all
+ * have eta_K < theta_c eta_max and n_K > 1; the mesh stays 2:1 balanced
+ * across faces (refinement wins: coarser face neighbours are refined until
+ * no leaf faces one two levels finer, and a merge that would face such a
+ * leaf is dropped).  The state (zeta, q, c) moves to the new cells by the
+ * L2 projection (eq:cons-remap): a child takes its parent's polynomial, a
+ * parent the exact-mass projection of its four children.  A child inherits
+ * its parent's Manning coefficient and bed offset, a parent takes the mean
+ * of its children's.  New cells are ordered by level, then row j, then
+ * column i (sw_cells lists them); every cell starts at degree r; the
+ * bathymetry of all cells is sampled from the raster of sw_set_bed_grid
+ * (SW_EINVAL without one).  Time, time step, tide and CFL number carry over;
+ * the boundary data of state and discharge sides must be given again
+ * (sw_set_boundary_state), and the per-launch-shape choices of
+ * sw_set_workgroup / sw_autotune return to their defaults.  All arrays sized
+ * by the mesh change with it (sw_counts).  out (may be NULL) receives the
+ * statistics.  The handle c stays valid; the call synchronises.  Errors:
+ * SW_EINVAL (batched context, open step, bad parameters, no raster),
+ * SW_ENOMEM, SW_EHIP; the context is unchanged on error. */
+sw_status sw_remesh(sw_ctx *c, const sw_amr_params *params, sw_amr_stats *out);
+/* Host outputs [n_cells]: level, i and j of every cell (any may be NULL). */
+sw_status sw_cells(const sw_ctx *c, int32_t *level_host, int32_t *i_host, int32_t *j_host);
+
 /* sw_tracer_step: advances the context's tracer by one recorded step with
  * the flow given, not solved: the tracer solve of eq:algebraic_concentration
  * with H(zeta^(l)) and the tracer residual R (eq:r_concentration) of every

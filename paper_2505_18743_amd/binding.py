@@ -27,7 +27,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
            "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
-           "sw_ens_autotune"]
+           "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -48,6 +48,20 @@ class SwParams(ctypes.Structure):
                 ("tide_period", ctypes.c_double), ("tide_phase", ctypes.c_double), ("tide_c_in", ctypes.c_double),
                 ("tracer_diff", ctypes.c_double), ("tracer_strain", ctypes.c_double),
                 ("tracer_decay", ctypes.c_double), ("quadrature", ctypes.c_int32)]
+
+
+class SwAmrParams(ctypes.Structure):
+    _fields_ = [("indicator", ctypes.c_int32), ("theta_r", ctypes.c_double), ("theta_c", ctypes.c_double),
+                ("n_max", ctypes.c_int32), ("h_min", ctypes.c_double)]
+
+
+class SwAmrStats(ctypes.Structure):
+    _fields_ = [("n_cells_old", ctypes.c_int64), ("n_cells_new", ctypes.c_int64), ("n_refined", ctypes.c_int64),
+                ("n_coarsened", ctypes.c_int64), ("eta_max", ctypes.c_double), ("mass_old", ctypes.c_double),
+                ("mass_new", ctypes.c_double), ("q_bathy", ctypes.c_double)]
+
+
+AMR_INDICATOR = {"vorticity": 0, "tracer_grad": 1}
 
 
 class SwDiag(ctypes.Structure):
@@ -95,6 +109,11 @@ def load():
                               ctypes.POINTER(ctypes.c_int32)]
     L.sw_ens_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p]
     L.sw_vjp_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    L.sw_set_bed_grid.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, vp]
+    L.sw_amr_indicator.argtypes = [vp, ctypes.c_int32, vp]
+    L.sw_remesh.argtypes = [vp, ctypes.POINTER(SwAmrParams), ctypes.POINTER(SwAmrStats)]
+    L.sw_cells.argtypes = [vp, vp, vp, vp]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
     L.sw_last_error.restype = ctypes.c_char_p
@@ -422,6 +441,42 @@ class Solver:
 
     def sync(self):
         _check(load().sw_sync(self.h), "sw_sync")
+
+    # ---- dynamic h-adaptivity ----
+    def set_bed_grid(self, grid):
+        """Bathymetry raster: grid = dict(x0, y0, dx, dy, b [ny, nx]) of bed
+        elevations; sampled at every node now and after every remesh."""
+        b = np.asarray(grid["b"], dtype=np.float64)
+        ny, nx = b.shape
+        t = self._dev(b, nx * ny)
+        _check(load().sw_set_bed_grid(self.h, int(nx), int(ny), float(grid["x0"]), float(grid["y0"]),
+                                      float(grid["dx"]), float(grid["dy"]), _ptr(t)), "sw_set_bed_grid")
+        self._keep_g = t
+
+    def amr_indicator(self, kind="vorticity"):
+        eta = torch.zeros(self.n_cells, dtype=torch.float64, device=self.dev)
+        _check(load().sw_amr_indicator(self.h, AMR_INDICATOR[kind], _ptr(eta)), "sw_amr_indicator")
+        return eta
+
+    def cells(self):
+        """(level, i, j) of every cell."""
+        out = [np.zeros(self.n_cells, dtype=np.int32) for _ in range(3)]
+        _check(load().sw_cells(self.h, *[o.ctypes.data_as(ctypes.c_void_p) for o in out]), "sw_cells")
+        return out
+
+    def remesh(self, indicator="vorticity", theta_r=1e-4, theta_c=5e-5, n_max=2, h_min=0.0):
+        """sw_remesh; returns its statistics.  Sizes and the mesh description
+        follow the new mesh."""
+        ap = SwAmrParams(AMR_INDICATOR[indicator], float(theta_r), float(theta_c), int(n_max), float(h_min))
+        st = SwAmrStats()
+        _check(load().sw_remesh(self.h, ctypes.byref(ap), ctypes.byref(st)), "sw_remesh")
+        nc, nv, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().sw_counts(self.h, ctypes.byref(nc), ctypes.byref(nv), ctypes.byref(nd)), "sw_counts")
+        self.n_cells, self.n_vol, self.n_dofs = nc.value, nv.value, nd.value
+        lev, ii, jj = self.cells()
+        self.meshes[0] = dict(self.meshes[0], level=lev, i=ii, j=jj)
+        self._member_index = None
+        return {k: getattr(st, k) for k, _ in SwAmrStats._fields_}
 
     # ---- adjoint ----
     def vjp_operator(self, eta, qx, qy, Fb, Gxb, Gyb, t=0.0):

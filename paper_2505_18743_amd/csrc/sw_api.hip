@@ -1,11 +1,13 @@
 // Host side of the C ABI declared in include/sw.h: validation, quadtree faces,
 // reference tables, device memory, and the per-step launch sequence.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "sw.h"
@@ -269,6 +271,8 @@ struct LevelH {
   double* d_vtab = nullptr;
   LevelTabs vtabs{};
   size_t voff = 0;
+  double* d_xh = nullptr;    // [S] sample-node positions on [0, 1]
+  double* d_xv = nullptr;    // [nv] volume-rule node positions (SW_QUAD_PAPER)
 };
 
 }  // namespace
@@ -284,6 +288,8 @@ struct sw_ctx {
   // members: coarse-grid origin and cell size; per cell: member, index in the
   // member's description, level, integer position, size
   std::vector<double> mx0, my0, mdx0;
+  std::vector<int> mnx0, mny0;
+  std::vector<std::array<int, 4>> mbc;
   std::vector<int> cmem, cloc, lev, ci, cj;
   std::vector<double> cdx;
   std::vector<LevelH> lv;
@@ -293,6 +299,13 @@ struct sw_ctx {
   double* d_lres = nullptr;   // IMEX: implicit-part residuals [slot][2][K][NP]
   double* d_gam = nullptr;    // IMEX: friction matrix of the last volume pass [K][NP(NP+1)/2]
   int *d_fA = nullptr, *d_fB = nullptr, *d_meta = nullptr, *d_err = nullptr, *d_cmem = nullptr;
+  int *d_ci = nullptr, *d_cj = nullptr;   // [K] integer cell positions
+  double* d_mxy = nullptr;                // [2][M] member origins
+  // bathymetry raster (sw_set_bed_grid): bed elevation g[j][i] at
+  // (gx0 + i gdx, gy0 + j gdy); sampled at the nodes of new cells by sw_remesh
+  double* d_grid = nullptr;
+  int gnx = 0, gny = 0;
+  double gx0 = 0, gy0 = 0, gdx = 0, gdy = 0;
   double *d_zb = nullptr, *d_braw = nullptr, *d_db = nullptr, *d_bvec = nullptr, *d_zmax = nullptr;
   double *d_nman = nullptr, *d_cdx = nullptr, *d_cw1 = nullptr, *d_zf = nullptr;
   double *d_sn[4]{}, *d_ss[4]{};
@@ -343,13 +356,28 @@ struct sw_ctx {
     *p = (T*)q;
     return SW_OK;
   }
-  ~sw_ctx() {
+  sw_ctx() = default;
+  sw_ctx(const sw_ctx&) = delete;
+  sw_ctx& operator=(const sw_ctx&) = default;
+  void release() {
     for (auto& e : ev) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
     }
+    ev.clear();
     for (void* q : allocs) (void)hipFree(q);
+    allocs.clear();
   }
+  // Releases this context's device memory and events and takes over n's
+  // contents (sw_remesh swaps in the context of the new mesh this way, so the
+  // caller's handle stays valid); n is left owning nothing.
+  void adopt(sw_ctx& n) {
+    release();
+    *this = n;
+    n.allocs.clear();
+    n.ev.clear();
+  }
+  ~sw_ctx() { release(); }
   // bracket a group of launches of one kernel class with events when profiling
   struct Scope {
     sw_ctx* c;
@@ -546,6 +574,9 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.S = S;
   L.w1 = L.wh[0];
   L.vtabs = L.tabs;
+  st = c->alloc(&L.d_xh, (size_t)S);
+  if (st != SW_OK) return st;
+  HIPCHK(hipMemcpy(L.d_xh, L.xh.data(), S * sizeof(double), hipMemcpyHostToDevice));
   if (c->nv > 0) {
     // the volume terms' Gauss-Legendre rule (Table 1): weights, basis values
     // and derivatives at its nodes, and their weighted forms; the mass-matrix
@@ -574,6 +605,9 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
     L.vtabs.wd = L.d_vtab + v_wd;
     L.vtabs.fl = nullptr;
     L.vtabs.S = nv;
+    st = c->alloc(&L.d_xv, (size_t)nv);
+    if (st != SW_OK) return st;
+    HIPCHK(hipMemcpy(L.d_xv, L.xv.data(), nv * sizeof(double), hipMemcpyHostToDevice));
   }
   return SW_OK;
 }
@@ -976,6 +1010,9 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     c->mx0.push_back(md.x0);
     c->my0.push_back(md.y0);
     c->mdx0.push_back(md.dx0);
+    c->mnx0.push_back(md.nx0);
+    c->mny0.push_back(md.ny0);
+    c->mbc.push_back({md.bc[0], md.bc[1], md.bc[2], md.bc[3]});
     long double area = 0.0L;
     leaf[m].reserve((size_t)md.n_cells * 2);
     for (int k = 0; k < md.n_cells; ++k) {
@@ -1152,6 +1189,9 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     ALLOC(c->d_meta, c->F);
     ALLOC(c->d_err, 1);
     ALLOC(c->d_cmem, K);
+    ALLOC(c->d_ci, K);
+    ALLOC(c->d_cj, K);
+    ALLOC(c->d_mxy, (size_t)2 * M);
     ALLOC(c->d_zb, (size_t)(c->nvol + c->nvv));
     ALLOC(c->d_braw, (size_t)(c->nvol + c->nvv));
     ALLOC(c->d_db, K);
@@ -1249,6 +1289,13 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   H2D(c->d_fB, fB.data(), c->F);
   H2D(c->d_meta, meta.data(), c->F);
   H2D(c->d_cmem, c->cmem.data(), K);
+  H2D(c->d_ci, c->ci.data(), K);
+  H2D(c->d_cj, c->cj.data(), K);
+  {
+    std::vector<double> mxy(c->mx0);
+    mxy.insert(mxy.end(), c->my0.begin(), c->my0.end());
+    H2D(c->d_mxy, mxy.data(), (size_t)2 * M);
+  }
   H2D(c->d_cdx, c->cdx.data(), K);
   H2D(c->d_cw1, cw1.data(), K);
   H2D(c->d_mtide, mtide.data(), 4 * (size_t)M);
@@ -1757,6 +1804,510 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
   }
   point(nullptr);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Dynamic h-adaptivity (Sec. 3.3 refinement criteria; Sec. 3.4 conservative
+// remap, eq:cons-remap, and the mass source Q^n, eq:mass-loss)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device buffer freed at scope exit (the call synchronises its stream first).
+struct TmpBuf {
+  void* p = nullptr;
+  ~TmpBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Bed elevation at every node of the context from its raster, then the depth
+// samples, face samples and per-cell tables (as sw_set_bathymetry).
+sw_status sample_grid(sw_ctx* c) {
+  for (auto& L : c->lv) {
+    RasterArgs a{};
+    a.g = c->d_grid;
+    a.gnx = c->gnx;
+    a.gny = c->gny;
+    a.gx0 = c->gx0;
+    a.gy0 = c->gy0;
+    a.gdx = c->gdx;
+    a.gdy = c->gdy;
+    a.cell0 = L.cell0;
+    a.ncell = L.ncell;
+    a.n = L.S;
+    a.off = L.off;
+    a.xh = L.d_xh;
+    a.ci = c->d_ci;
+    a.cj = c->d_cj;
+    a.cdx = c->d_cdx;
+    a.cmem = c->d_cmem;
+    a.mxy = c->d_mxy;
+    a.M = c->M;
+    a.braw = c->d_braw;
+    HIPCHK(launch_amr_raster(a, c->s));
+    if (c->nv > 0) {   // the volume rule's nodes (SW_QUAD_PAPER)
+      a.n = c->nv;
+      a.off = L.voff;
+      a.xh = L.d_xv;
+      HIPCHK(launch_amr_raster(a, c->s));
+    }
+  }
+  c->bathy_set = true;
+  return rebake(c);
+}
+
+// eta_K of every cell at the context's state, at the nodes of the volume
+// integrals (those carry bathymetry samples)
+sw_status amr_eta(sw_ctx* c, int kind, double* eta) {
+  for (auto& L : c->lv) {
+    const LevelTabs& t = c->nv > 0 ? L.vtabs : L.tabs;
+    AmrEtaArgs a{};
+    a.l = t.l;
+    a.d = t.d;
+    a.n = t.S;
+    a.N1 = c->N1;
+    a.cell0 = L.cell0;
+    a.ncell = L.ncell;
+    a.zb = c->d_zb + (c->nv > 0 ? L.voff : L.off);
+    a.cdx = c->d_cdx;
+    a.z = c->d_sn[0];
+    a.qx = c->d_sn[1];
+    a.qy = c->d_sn[2];
+    a.c = c->d_sn[3];
+    a.eps = c->p.eps;
+    a.kind = kind;
+    a.eta = eta;
+    HIPCHK(launch_amr_eta(a, c->s));
+  }
+  return SW_OK;
+}
+
+// Total mass sum_K int h and sum_K int z_b l of the current state on the
+// sample rule (synchronises).
+sw_status amr_mass(sw_ctx* c, double& mass, double& bathy) {
+  TmpBuf b;
+  HIPCHK(hipMalloc(&b.p, sizeof(double) * (2 * (size_t)c->K + 2)));
+  double* v = (double*)b.p;
+  for (auto& L : c->lv) {
+    AmrMassArgs a{};
+    a.l = L.tabs.l;
+    a.w = L.tabs.w;
+    a.S = L.S;
+    a.N1 = c->N1;
+    a.cell0 = L.cell0;
+    a.ncell = L.ncell;
+    a.zb = c->d_zb + L.off;
+    a.cdx = c->d_cdx;
+    a.z = c->d_sn[0];
+    a.out = v;
+    HIPCHK(launch_amr_mass(a, c->s));
+  }
+  HIPCHK(launch_amr_sum2(v, c->K, v + 2 * (size_t)c->K, c->s));
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, v + 2 * (size_t)c->K, sizeof(h), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  mass = h[0];
+  bathy = h[1];
+  return SW_OK;
+}
+
+// The degree decision and remap that start the next step, if not in place
+// (the state the adaptivity acts on; a previous step's final kernel did it).
+sw_status ensure_start(sw_ctx* c) {
+  if (c->start_ready) return SW_OK;
+  sw_status st = elements(c, F_START, M_START, -1, 0, 0, nullptr, 0, 0);
+  if (st != SW_OK) return st;
+  c->start_ready = true;
+  return SW_OK;
+}
+
+// The adapted quadtree of one member (see sw_remesh): new leaves in (level,
+// j, i) order and, per leaf, the source of its state.
+struct AmrPlan {
+  std::vector<int> lev, ci, cj, type, src;   // src: 4 per new leaf
+  int64_t n_refined = 0, n_coarsened = 0;
+};
+
+AmrPlan amr_plan(const sw_ctx* c, const std::vector<double>& eta, double eta_max, const sw_amr_params& ap) {
+  const int K = c->K;
+  const int nx0 = c->mnx0[0], ny0 = c->mny0[0];
+  const bool perx = c->mbc[0][0] == SW_BC_PERIODIC, pery = c->mbc[0][2] == SW_BC_PERIODIC;
+  auto kL = [](int64_t k) { return (int)(k >> 52); };
+  auto ki = [](int64_t k) { return (int)((k >> 26) & ((1 << 26) - 1)); };
+  auto kj = [](int64_t k) { return (int)(k & ((1 << 26) - 1)); };
+  // face neighbour position at level L (periodic sides wrap); false outside
+  auto neighbour = [&](int L, int i, int j, int di, int dj, int& ni, int& nj) {
+    const int nxL = nx0 << L, nyL = ny0 << L;
+    ni = i + di;
+    nj = j + dj;
+    if (ni < 0 || ni >= nxL) {
+      if (!perx) return false;
+      ni = (ni + nxL) % nxL;
+    }
+    if (nj < 0 || nj >= nyL) {
+      if (!pery) return false;
+      nj = (nj + nyL) % nyL;
+    }
+    return true;
+  };
+  std::vector<char> refine(K), coarsen(K);
+  for (int k = 0; k < K; ++k) {
+    const double dx = c->cdx[k];
+    refine[k] = eta[k] > ap.theta_r * eta_max && c->lev[k] + 1 < ap.n_max && dx > ap.h_min;
+    coarsen[k] = eta[k] < ap.theta_c * eta_max && c->lev[k] > 0 && !refine[k];
+  }
+  std::unordered_map<int64_t, int> old;
+  old.reserve((size_t)K * 2);
+  for (int k = 0; k < K; ++k) old.emplace(key(c->lev[k], c->ci[k], c->cj[k]), k);
+  std::unordered_set<int64_t> leaves;
+  leaves.reserve((size_t)K * 4);
+  auto split = [&](int64_t k) {
+    leaves.erase(k);
+    const int L = kL(k), i = ki(k), j = kj(k);
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) leaves.insert(key(L + 1, 2 * i + a, 2 * j + b));
+  };
+  for (int k = 0; k < K; ++k) {
+    const int64_t kk = key(c->lev[k], c->ci[k], c->cj[k]);
+    if (refine[k]) {
+      leaves.insert(kk);
+      split(kk);
+    } else {
+      leaves.insert(kk);
+    }
+  }
+  // 2:1 balance across faces: refine every leaf two or more levels coarser
+  // than a face neighbour, until none is left
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (bool changed = true; changed;) {
+    changed = false;
+    std::vector<int64_t> cur(leaves.begin(), leaves.end());
+    std::sort(cur.begin(), cur.end());
+    for (int64_t kk : cur) {
+      if (!leaves.count(kk)) continue;
+      const int L = kL(kk), i = ki(kk), j = kj(kk);
+      for (int sd = 0; sd < 4; ++sd) {
+        int ni, nj;
+        if (!neighbour(L, i, j, di[sd], dj[sd], ni, nj)) continue;
+        for (int A = L - 2; A >= 0; --A) {
+          const int64_t ck = key(A, ni >> (L - A), nj >> (L - A));
+          if (leaves.count(ck)) {
+            split(ck);
+            changed = true;
+            break;
+          }
+        }
+      }
+    }
+  }
+  AmrPlan P;
+  for (auto& kv : old)
+    if (!leaves.count(kv.first)) ++P.n_refined;
+  // merges of four flagged sibling leaves that keep the balance
+  std::vector<int64_t> parents;
+  for (int k = 0; k < K; ++k)
+    if (coarsen[k]) parents.push_back(key(c->lev[k] - 1, c->ci[k] >> 1, c->cj[k] >> 1));
+  std::sort(parents.begin(), parents.end());
+  parents.erase(std::unique(parents.begin(), parents.end()), parents.end());
+  std::vector<int64_t> merged;
+  for (int64_t pk : parents) {
+    const int L = kL(pk), pi = ki(pk), pj = kj(pk);
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b)
+      for (int a = 0; a < 2 && ok; ++a) {
+        const int64_t kd = key(L + 1, 2 * pi + a, 2 * pj + b);
+        auto it = old.find(kd);
+        ok = it != old.end() && leaves.count(kd) && coarsen[it->second];
+      }
+    for (int sd = 0; sd < 4 && ok; ++sd) {
+      int ni, nj;
+      if (!neighbour(L, pi, pj, di[sd], dj[sd], ni, nj)) continue;
+      for (int t = 0; t < 4 && ok; ++t) {
+        int ci, cj;   // level L + 2 cells of the neighbour square along the side
+        if (sd == 0) ci = 4 * ni + 3, cj = 4 * nj + t;
+        else if (sd == 1) ci = 4 * ni, cj = 4 * nj + t;
+        else if (sd == 2) ci = 4 * ni + t, cj = 4 * nj + 3;
+        else ci = 4 * ni + t, cj = 4 * nj;
+        if (leaves.count(key(L + 2, ci, cj))) ok = false;
+      }
+    }
+    if (ok) merged.push_back(pk);
+  }
+  for (int64_t pk : merged) {
+    const int L = kL(pk), pi = ki(pk), pj = kj(pk);
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) leaves.erase(key(L + 1, 2 * pi + a, 2 * pj + b));
+    leaves.insert(pk);
+  }
+  P.n_coarsened = (int64_t)merged.size();
+  std::vector<std::array<int, 3>> nl;
+  nl.reserve(leaves.size());
+  for (int64_t kk : leaves) nl.push_back({kL(kk), kj(kk), ki(kk)});
+  std::sort(nl.begin(), nl.end());
+  for (auto& e : nl) {
+    const int L = e[0], j = e[1], i = e[2];
+    P.lev.push_back(L);
+    P.ci.push_back(i);
+    P.cj.push_back(j);
+    auto it = old.find(key(L, i, j));
+    if (it != old.end()) {
+      P.type.push_back(0);
+      P.src.insert(P.src.end(), {it->second, 0, 0, 0});
+      continue;
+    }
+    if (L > 0 && (it = old.find(key(L - 1, i >> 1, j >> 1))) != old.end()) {
+      P.type.push_back(1);
+      P.src.insert(P.src.end(), {it->second, 2 * (j & 1) + (i & 1), 0, 0});
+      continue;
+    }
+    P.type.push_back(2);
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        auto kd = old.find(key(L + 1, 2 * i + a, 2 * j + b));
+        P.src.push_back(kd == old.end() ? -1 : kd->second);
+      }
+  }
+  return P;
+}
+
+// Transfer tables of degree r on the unit square: child[s][j][k] = psi_k at
+// child s's support point j (s = 2 sy + sx); proj[s][j][k]: the exact-mass L2
+// projection's part from child s, parent_j = sum_s sum_k proj[s][j][k] child_s,k.
+bool transfer_tables(int r, std::vector<double>& child, std::vector<double>& proj) {
+  const int N1 = r + 1, NP = N1 * N1;
+  std::vector<double> xi, wb, xg, wg;
+  gll(N1, xi, wb);
+  gl(N1, xg, wg);
+  child.assign((size_t)4 * NP * NP, 0.0);
+  proj.assign((size_t)4 * NP * NP, 0.0);
+  std::vector<double> Mq((size_t)NP * NP, 0.0);
+  for (int i = 0; i < NP; ++i)
+    for (int j = 0; j < NP; ++j) {
+      double s = 0.0;
+      for (int b = 0; b < N1; ++b)
+        for (int a = 0; a < N1; ++a)
+          s += wg[a] * wg[b] * lag(xi, i % N1, xg[a]) * lag(xi, i / N1, xg[b]) * lag(xi, j % N1, xg[a]) *
+               lag(xi, j / N1, xg[b]);
+      Mq[(size_t)i * NP + j] = s;
+    }
+  if (!spd_inverse(Mq, NP)) return false;
+  for (int s = 0; s < 4; ++s) {
+    const int sx = s & 1, sy = s >> 1;
+    double* T = child.data() + (size_t)s * NP * NP;
+    for (int j = 0; j < NP; ++j) {
+      const double X = 0.5 * (sx + xi[j % N1]), Y = 0.5 * (sy + xi[j / N1]);
+      for (int k = 0; k < NP; ++k) T[(size_t)j * NP + k] = lag(xi, k % N1, X) * lag(xi, k / N1, Y);
+    }
+    std::vector<double> rhs((size_t)NP * NP, 0.0);   // int_child psi_i^parent psi_k^child
+    for (int i = 0; i < NP; ++i)
+      for (int k = 0; k < NP; ++k) {
+        double acc = 0.0;
+        for (int b = 0; b < N1; ++b)
+          for (int a = 0; a < N1; ++a)
+            acc += 0.25 * wg[a] * wg[b] * lag(xi, i % N1, 0.5 * (sx + xg[a])) * lag(xi, i / N1, 0.5 * (sy + xg[b])) *
+                   lag(xi, k % N1, xg[a]) * lag(xi, k / N1, xg[b]);
+        rhs[(size_t)i * NP + k] = acc;
+      }
+    double* Pm = proj.data() + (size_t)s * NP * NP;
+    for (int j = 0; j < NP; ++j)
+      for (int k = 0; k < NP; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < NP; ++i) acc += Mq[(size_t)j * NP + i] * rhs[(size_t)i * NP + k];
+        Pm[(size_t)j * NP + k] = acc;
+      }
+  }
+  return true;
+}
+
+sw_status amr_common_checks(sw_ctx* c) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (c->M != 1) return fail(SW_EINVAL, "mesh adaptivity covers single-member contexts");
+  if (c->stage_done != 0) return fail(SW_EINVAL, "mesh adaptivity cannot run inside an open step");
+  return need_bathy(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_cells(const sw_ctx* c, int32_t* level, int32_t* i, int32_t* j) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  for (int k = 0; k < c->K; ++k) {
+    if (level) level[k] = c->lev[k];
+    if (i) i[k] = c->ci[k];
+    if (j) j[k] = c->cj[k];
+  }
+  return SW_OK;
+}
+
+sw_status sw_set_bed_grid(sw_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double dx, double dy,
+                          const double* b) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!b) return fail(SW_EINVAL, "b is NULL");
+  if (nx < 2 || ny < 2 || (int64_t)nx * ny > ((int64_t)1 << 31))
+    return fail(SW_EINVAL, "the raster needs 2 <= nx, ny and nx ny <= 2^31");
+  if (!(dx > 0.0 && dx < 1e300) || !(dy > 0.0 && dy < 1e300) || !(std::fabs(x0) < 1e300) ||
+      !(std::fabs(y0) < 1e300))
+    return fail(SW_EINVAL, "raster spacing must be finite and > 0, its origin finite");
+  const size_t n = (size_t)nx * ny;
+  if (!c->d_grid || (size_t)c->gnx * c->gny != n) {
+    if (c->d_grid) {   // the previous raster's memory
+      HIPCHK(hipStreamSynchronize(c->s));
+      auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_grid);
+      if (it != c->allocs.end()) c->allocs.erase(it);
+      HIPCHK(hipFree(c->d_grid));
+      c->d_grid = nullptr;
+    }
+    sw_status st = c->alloc(&c->d_grid, n);
+    if (st != SW_OK) return st;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_grid, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+  c->gnx = nx;
+  c->gny = ny;
+  c->gx0 = x0;
+  c->gy0 = y0;
+  c->gdx = dx;
+  c->gdy = dy;
+  return sample_grid(c);
+}
+
+sw_status sw_amr_indicator(sw_ctx* c, int32_t kind, double* eta) {
+  sw_status st = amr_common_checks(c);
+  if (st != SW_OK) return st;
+  if (!eta) return fail(SW_EINVAL, "eta is NULL");
+  if (kind != SW_AMR_VORTICITY && kind != SW_AMR_TRACER_GRAD) return fail(SW_EINVAL, "unknown indicator");
+  if (kind == SW_AMR_TRACER_GRAD && !c->p.tracer) return fail(SW_EINVAL, "the tracer indicator needs a tracer");
+  if ((st = ensure_start(c)) != SW_OK) return st;
+  return amr_eta(c, kind, eta);
+}
+
+sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
+  sw_status st = amr_common_checks(c);
+  if (st != SW_OK) return st;
+  if (!ap) return fail(SW_EINVAL, "NULL adaptivity parameters");
+  if (ap->indicator != SW_AMR_VORTICITY && ap->indicator != SW_AMR_TRACER_GRAD)
+    return fail(SW_EINVAL, "unknown indicator");
+  if (ap->indicator == SW_AMR_TRACER_GRAD && !c->p.tracer)
+    return fail(SW_EINVAL, "the tracer indicator needs a tracer");
+  if (!(ap->theta_r >= 0.0 && ap->theta_r < 1e300) || !(ap->theta_c >= 0.0 && ap->theta_c < 1e300) ||
+      !(ap->h_min >= 0.0 && ap->h_min < 1e300))
+    return fail(SW_EINVAL, "theta_r, theta_c and h_min must be finite and >= 0");
+  if (ap->n_max < 1 || ap->n_max > c->p.n_levels)
+    return fail(SW_EINVAL, "n_max must be 1 .. n_levels (params.S gives every level's sample count)");
+  if (!c->d_grid) return fail(SW_EINVAL, "sw_remesh samples new cells from the raster of sw_set_bed_grid");
+  if ((st = ensure_start(c)) != SW_OK) return st;
+  const int K = c->K;
+  std::vector<double> eta(K);
+  {
+    TmpBuf b;
+    HIPCHK(hipMalloc(&b.p, sizeof(double) * (size_t)std::max(K, 1)));
+    if ((st = amr_eta(c, ap->indicator, (double*)b.p)) != SW_OK) return st;
+    HIPCHK(hipMemcpyAsync(eta.data(), b.p, sizeof(double) * K, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+  }
+  double eta_max = 0.0;
+  for (double e : eta) eta_max = std::max(eta_max, e);
+  sw_amr_stats S{};
+  S.n_cells_old = K;
+  S.eta_max = eta_max;
+  if ((st = amr_mass(c, S.mass_old, S.q_bathy)) != SW_OK) return st;
+  const double bathy_old = S.q_bathy;
+  AmrPlan P = amr_plan(c, eta, eta_max, *ap);
+  S.n_refined = P.n_refined;
+  S.n_coarsened = P.n_coarsened;
+  S.n_cells_new = (int64_t)P.lev.size();
+  if (P.n_refined == 0 && P.n_coarsened == 0) {
+    S.mass_new = S.mass_old;
+    S.q_bathy = 0.0;
+    if (out) *out = S;
+    return SW_OK;
+  }
+  for (int v : P.src)
+    if (v < 0) return fail(SW_EINVAL, "sw_remesh: a new cell has no source cell");
+  std::vector<double> tchild, tproj;
+  if (!transfer_tables(c->r, tchild, tproj)) return fail(SW_EINVAL, "sw_remesh: mass matrix not SPD");
+  // the context of the new mesh, on the same stream with the same parameters
+  sw_mesh_desc md{};
+  md.nx0 = c->mnx0[0];
+  md.ny0 = c->mny0[0];
+  md.x0 = c->mx0[0];
+  md.y0 = c->my0[0];
+  md.dx0 = c->mdx0[0];
+  md.n_cells = (int32_t)P.lev.size();
+  md.level = P.lev.data();
+  md.i = P.ci.data();
+  md.j = P.cj.data();
+  for (int sd = 0; sd < 4; ++sd) md.bc[sd] = c->mbc[0][sd];
+  sw_ctx* n = nullptr;
+  if ((st = sw_create_batch(&n, 1, &md, &c->p, c->s)) != SW_OK) return st;
+  auto drop = [&](sw_status e) {
+    (void)hipStreamSynchronize(c->s);
+    delete n;
+    return e;
+  };
+  const int Kn = n->K, NP = c->NP;
+  TmpBuf bt, bs, btab;
+  auto d2d = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->s);
+  };
+  hipError_t e = hipSuccess;
+  // member time, time step, tide, CFL number and diagnostics carry over
+  if (e == hipSuccess) e = d2d(n->d_mt, c->d_mt, sizeof(double));
+  if (e == hipSuccess) e = d2d(n->d_mdt, c->d_mdt, sizeof(double));
+  if (e == hipSuccess) e = d2d(n->d_mtide, c->d_mtide, 4 * sizeof(double));
+  if (e == hipSuccess) e = d2d(n->d_mcfl, c->d_mcfl, sizeof(double));
+  if (e == hipSuccess) e = d2d(n->d_mdiag, c->d_mdiag, kMDiag * sizeof(double));
+  if (e == hipSuccess && n->alloc(&n->d_grid, (size_t)c->gnx * c->gny) != SW_OK) e = hipErrorOutOfMemory;
+  if (e == hipSuccess) e = d2d(n->d_grid, c->d_grid, sizeof(double) * (size_t)c->gnx * c->gny);
+  if (e == hipSuccess) e = hipMalloc(&bt.p, sizeof(int) * (size_t)Kn);
+  if (e == hipSuccess) e = hipMalloc(&bs.p, sizeof(int) * 4 * (size_t)Kn);
+  if (e == hipSuccess) e = hipMalloc(&btab.p, sizeof(double) * 8 * (size_t)NP * NP);
+  if (e == hipSuccess) e = hipMemcpyAsync(bt.p, P.type.data(), sizeof(int) * Kn, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(bs.p, P.src.data(), sizeof(int) * 4 * Kn, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(btab.p, tchild.data(), sizeof(double) * 4 * NP * NP, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((double*)btab.p + 4 * NP * NP, tproj.data(), sizeof(double) * 4 * NP * NP,
+                       hipMemcpyHostToDevice, c->s);
+  if (e != hipSuccess) return drop(fail(SW_EHIP, std::string("sw_remesh: ") + hipGetErrorString(e)));
+  n->gnx = c->gnx;
+  n->gny = c->gny;
+  n->gx0 = c->gx0;
+  n->gy0 = c->gy0;
+  n->gdx = c->gdx;
+  n->gdy = c->gdy;
+  AmrXferArgs x{};
+  x.Kn = Kn;
+  x.NP = NP;
+  x.type = (const int*)bt.p;
+  x.src = (const int*)bs.p;
+  x.tchild = (const double*)btab.p;
+  x.tproj = (const double*)btab.p + 4 * NP * NP;
+  for (int f = 0; f < 4; ++f) {
+    x.in[f] = c->d_sn[f];
+    x.out[f] = n->d_sn[f];
+  }
+  x.nman_in = c->d_nman;
+  x.db_in = c->d_db;
+  x.nman_out = n->d_nman;
+  x.db_out = n->d_db;
+  if ((e = launch_amr_transfer(x, c->s)) != hipSuccess)
+    return drop(fail(SW_EHIP, std::string("sw_remesh: ") + hipGetErrorString(e)));
+  // the bathymetry of the new cells (with the transferred bed offsets)
+  if ((st = sample_grid(n)) != SW_OK) return drop(st);
+  double bathy_new = 0.0;
+  if ((st = amr_mass(n, S.mass_new, bathy_new)) != SW_OK) return drop(st);
+  S.q_bathy = bathy_new - bathy_old;
+  n->prof = c->prof;
+  n->prof_mask = c->prof_mask;
+  n->nstep = c->nstep;
+  HIPCHK(hipStreamSynchronize(c->s));
+  c->adopt(*n);
+  delete n;
+  if (out) *out = S;
+  return SW_OK;
 }
 
 }  // extern "C"

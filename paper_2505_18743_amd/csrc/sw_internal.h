@@ -182,6 +182,58 @@ struct VjpFaceArgs {
 hipError_t launch_vjp_vol(int r, int P, int mode, const VjpArgs& a, int nblk, hipStream_t s);
 hipError_t launch_vjp_face(int r, const VjpFaceArgs& a, int nblk, hipStream_t s);
 
+// ---- dynamic h-adaptivity ------------------------------------------------
+struct AmrEtaArgs {
+  const double* l;       // [n][N1] basis values at the volume rule's nodes
+  const double* d;       // [n][N1] their derivatives
+  int n, N1, cell0, ncell;
+  const double* zb;      // level block of depth samples at those nodes [ncell][n(a)][n(b)]
+  const double* cdx;     // [K]
+  const double *z, *qx, *qy, *c;   // state [K][NP] (c may be NULL)
+  double eps;
+  int kind;              // 0: vorticity, 1: tracer gradient
+  double* eta;           // [K] out
+};
+struct AmrXferArgs {
+  int Kn, NP;
+  const int* type;       // [Kn] 0: same cell, 1: child of an old cell, 2: parent of four old cells
+  const int* src;        // [Kn][4] 0: old cell; 1: old parent, sub-cell 2 sy + sx; 2: old children by sub-cell
+  const double* tchild;  // [4][NP][NP] parent basis at each child's support points
+  const double* tproj;   // [4][NP][NP] exact-mass L2 projection, part of each child
+  const double* in[4];   // old state fields [K_old][NP]
+  double* out[4];        // new state fields [Kn][NP]
+  const double *nman_in, *db_in;
+  double *nman_out, *db_out;
+};
+struct RasterArgs {
+  const double* g;       // raster [gny][gnx]
+  int gnx, gny;
+  double gx0, gy0, gdx, gdy;
+  int cell0, ncell, n;   // level block and nodes per direction
+  size_t off;            // offset of the block's nodes in braw
+  const double* xh;      // [n] node positions on [0, 1]
+  const int *ci, *cj;    // [K] integer cell positions
+  const double* cdx;     // [K]
+  const int* cmem;       // [K] member of each cell
+  const double* mxy;     // [2][M] member origins (x0 of every member, then y0)
+  int M;
+  double* braw;          // bed elevation at the nodes (out)
+};
+struct AmrMassArgs {
+  const double* l;       // [S][N1] basis values at the sample nodes
+  const double* w;       // [S] rule weights
+  int S, N1, cell0, ncell;
+  const double* zb;      // level block [ncell][S(a)][S(b)]
+  const double* cdx;
+  const double* z;       // free surface [K][NP]
+  double* out;           // [K][2]: int h, int z_b l
+};
+hipError_t launch_amr_eta(const AmrEtaArgs& a, hipStream_t s);
+hipError_t launch_amr_transfer(const AmrXferArgs& a, hipStream_t s);
+hipError_t launch_amr_raster(const RasterArgs& a, hipStream_t s);
+hipError_t launch_amr_mass(const AmrMassArgs& a, hipStream_t s);
+hipError_t launch_amr_sum2(const double* v, int K, double* out, hipStream_t s);
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_stage(int r, int P, int mode, const StageArgs& a, int nblk, hipStream_t s);
 hipError_t launch_stage_scan(int r, int P, int mode, int mode2, const StageArgs& a, int nblk, hipStream_t s);

@@ -41,10 +41,11 @@ def test_struct_layouts_match_the_header(tmp_path):
     """Field offsets of the ctypes mirrors equal those gcc computes from sw.h."""
     import shutil
     import subprocess
-    from paper_2505_18743_amd.binding import SwDiag, SwMeshDesc, SwParams
+    from paper_2505_18743_amd.binding import SwAmrParams, SwAmrStats, SwDiag, SwMeshDesc, SwParams
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    structs = {"sw_mesh_desc": SwMeshDesc, "sw_params": SwParams, "sw_diag": SwDiag}
+    structs = {"sw_mesh_desc": SwMeshDesc, "sw_params": SwParams, "sw_diag": SwDiag,
+               "sw_amr_params": SwAmrParams, "sw_amr_stats": SwAmrStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sw.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
