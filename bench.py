@@ -584,6 +584,131 @@ def vortex_bench(device, N=320):
     return dict(workload="travelling_vortex_static_nmax5", T=T, runs=out)
 
 
+# Table 7, with AMR at n_max = 5: wall time (s, 8 CPU processes) and DoFs
+PAPER_VORTEX_AMR = [("rk32", 1, 74.1, 267_828), ("ssp3", 2, 286.7, 590_949), ("rk44", 3, 531.1, 1_028_256)]
+
+
+def vortex_amr_bench(device, nmax=5, N=20, cases=None):
+    """The travelling vortex with dynamic h-adaptivity as Sec. 4.4 runs it: the
+    paper's quadrature (Table 1), initial mesh 2N x N, refinement to n_max
+    levels on the vorticity indicator with theta_r = 1e-4, theta_c = 5e-5,
+    a remesh every 5 steps, the initial mesh adapted n_max - 1 times to the
+    initial state; beside it the static mesh of the finest level.  Both take
+    the fixed dt = T / ceil(T / (0.9 x the static finest mesh's positivity
+    bound at t = 0)); states are the exact solution at the support points.
+    Wall times cover the whole run on the GPU (remeshes included); the AMR
+    overhead is the time spent in sw_remesh."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from exact import Vortex
+    from workloads.gen import uniform_mesh_desc
+    from paper_2505_18743_amd import Solver
+    T = 1.0 / 6.0
+    v = Vortex()
+    Nf = N * 2 ** (nmax - 1)
+    grid = dict(x0=-1.0, y0=-1.0, dx=4.0, dy=3.0, b=np.zeros((2, 2)))
+    out = []
+
+    def inflow(x, y):
+        h, u, w = v.fields(x, y, 0.0)
+        return h, h * u, h * w, np.zeros_like(x)
+
+    def exact_at_dofs(s):
+        d = s.dof_coords()
+        h, u, w = v.fields(d[:, 0], d[:, 1], 0.0)
+        return [h, h * u, h * w]
+
+    # Gauss-Lobatto weights on [0, 1] at the r + 1 support points
+    gllw = {1: [0.5, 0.5], 2: [1 / 6, 2 / 3, 1 / 6], 3: [1 / 12, 5 / 12, 5 / 12, 1 / 12]}
+
+    def l2_at_dofs(s, r, dx0):
+        """L2 norm of the free-surface error at T by the support points' Lobatto
+        rule (area-weighted, so meshes of different refinement compare)."""
+        d = s.dof_coords()
+        he, _, _ = v.fields(d[:, 0], d[:, 1], T)
+        z = s.get_state()[0].cpu().numpy()
+        lev = s.cells()[0]
+        w1 = np.asarray(gllw[r])
+        w = (np.outer(w1, w1).ravel()[None, :] * (dx0 / 2.0 ** lev[:, None]) ** 2).ravel()
+        return float(np.sqrt(np.sum(w * (z - he) ** 2)))
+
+    for rk, r, paper_s, paper_dofs in (cases or PAPER_VORTEX_AMR):
+        params = dict(r=r, S=(r + 2,) * nmax, rule="gll", rk=rk, g=9.81, eps=1e-3, h_lim=0.0, eps0=1e-8,
+                      newton_max=20, cfl=0.9, cfl_mode=1, tracer=False, tide=(0.0, 1.0, 0.0, 0.0),
+                      adapt_degree=False, quadrature="paper")
+        bc = ("state", "open", "wall", "wall")
+        # static finest mesh
+        progress(f"vortex static N={Nf} {rk} r={r}")
+        st = Solver(uniform_mesh_desc(2 * Nf, Nf, 0.0, 0.0, 1.0 / Nf, bc=bc), dict(params, S=(r + 2,)),
+                    device=device)
+        st.set_bed_grid(grid)
+        st.set_manning(np.zeros(st.n_cells))
+        st.set_boundary_state(inflow)
+        u0 = exact_at_dofs(st)
+        dtb = float(st.apply_operator(*u0, None, 0.0)[4].cpu()[0])
+        n = int(math.ceil(T / (0.9 * dtb)))
+        dt = T / n
+        st.set_state(*u0)
+        st.run(3, dt)
+        st.sync()
+        st.set_state(*u0)
+        st.set_time(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run(n, dt)
+        st.sync()
+        torch.cuda.synchronize()
+        wall_static = time.perf_counter() - t0
+        err_static = l2_at_dofs(st, r, 1.0 / Nf)
+        dofs_static = 3 * (r + 1) ** 2 * st.n_cells
+        st.close()
+        # adaptive run
+        progress(f"vortex AMR n_max={nmax} {rk} r={r}")
+        s = Solver(uniform_mesh_desc(2 * N, N, 0.0, 0.0, 1.0 / N, bc=bc), params, device=device)
+        s.set_bed_grid(grid)
+        s.set_manning(np.zeros(s.n_cells))
+        s.set_boundary_state(inflow)
+        s.set_state(*exact_at_dofs(s))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_remesh = 0.0
+        n_remesh = 0
+        dof_max = 0
+        for _ in range(nmax - 1):
+            s.remesh("vorticity", 1e-4, 5e-5, nmax)
+            s.set_state(*exact_at_dofs(s))
+        s.set_boundary_state(inflow)
+        t_init = time.perf_counter() - t0
+        k = 0
+        while k < n:
+            m = min(5, n - k)
+            s.run(m, dt)
+            k += m
+            dof_max = max(dof_max, 3 * (r + 1) ** 2 * s.n_cells)
+            if k < n:
+                ta = time.perf_counter()
+                s.remesh("vorticity", 1e-4, 5e-5, nmax)
+                s.set_boundary_state(inflow)
+                t_remesh += time.perf_counter() - ta
+                n_remesh += 1
+        s.sync()
+        torch.cuda.synchronize()
+        wall_amr = time.perf_counter() - t0
+        out.append(dict(rk=rk, r=r, steps=n, dt=dt, remeshes=n_remesh,
+                        static=dict(cells=dofs_static // (3 * (r + 1) ** 2), dofs=dofs_static,
+                                    wall_s=round(wall_static, 3), l2_zeta_error=err_static),
+                        amr=dict(dofs_final=3 * (r + 1) ** 2 * s.n_cells, dofs_max=dof_max,
+                                 wall_s=round(wall_amr, 3), init_adapt_s=round(t_init, 3),
+                                 remesh_s=round(t_remesh, 3), amr_overhead=round((t_remesh + t_init) / wall_amr, 4),
+                                 l2_zeta_error=l2_at_dofs(s, r, 1.0 / N)),
+                        speedup_amr_vs_static=round(wall_static / wall_amr, 3),
+                        paper_amr_wall_s=paper_s, paper_amr_dofs=paper_dofs,
+                        paper_hardware="8 CPU processes (deal.II, MPI), whole run"))
+        s.close()
+    return dict(workload=f"travelling_vortex_amr_nmax{nmax}", T=T, runs=out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -600,7 +725,9 @@ def main():
                     "(0: library default)")
     ap.add_argument("--imex-steps", type=int, default=100, help="beach steps of the IMEX leg (0: skip)")
     ap.add_argument("--no-vortex", action="store_true", help="skip the travelling-vortex wall-time leg")
-    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex", "vortex"], default=None,
+    ap.add_argument("--no-vortex-amr", action="store_true", help="skip the adaptive travelling-vortex leg")
+    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex", "vortex", "vortex_amr"],
+                    default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
@@ -633,6 +760,9 @@ def main():
         return
     if args.only == "vortex":
         print(json.dumps(vortex_bench(dev)), flush=True)
+        return
+    if args.only == "vortex_amr":
+        print(json.dumps(vortex_amr_bench(dev)), flush=True)
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)

@@ -355,6 +355,18 @@ sw_status sw_amr_indicator(sw_ctx *c, int32_t indicator, double *eta_dev);
 sw_status sw_remesh(sw_ctx *c, const sw_amr_params *params, sw_amr_stats *out);
 /* Host outputs [n_cells]: level, i and j of every cell (any may be NULL). */
 sw_status sw_cells(const sw_ctx *c, int32_t *level_host, int32_t *i_host, int32_t *j_host);
+/* The mesh decision of sw_remesh on the host alone (no device work): for a
+ * mesh (cells sorted by level) and its indicator values eta_host [n_cells],
+ * the new leaves in sw_remesh's order (level_host, i_host, j_host [cap]) and
+ * where each takes its state from: type_host [cap] 0 (the same cell,
+ * src_host[4n] = its old index), 1 (a child: src_host[4n] = the old parent,
+ * src_host[4n+1] = 2 sy + sx of the child) or 2 (a parent: src_host[4n + 2 sy
+ * + sx] = the old children).  *n_new receives the new cell count; with cap
+ * below it the call returns SW_EINVAL and fills nothing else.  Output arrays
+ * may be NULL. */
+sw_status sw_amr_plan(const sw_mesh_desc *mesh, const double *eta_host, const sw_amr_params *params, int32_t cap,
+                      int32_t *n_new, int32_t *level_host, int32_t *i_host, int32_t *j_host, int32_t *type_host,
+                      int32_t *src_host, int64_t *n_refined, int64_t *n_coarsened);
 
 /* sw_tracer_step: advances the context's tracer by one recorded step with
  * the flow given, not solved: the tracer solve of eq:algebraic_concentration

@@ -27,7 +27,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
            "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
-           "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells"]
+           "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells", "sw_amr_plan"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -114,6 +114,9 @@ def load():
     L.sw_amr_indicator.argtypes = [vp, ctypes.c_int32, vp]
     L.sw_remesh.argtypes = [vp, ctypes.POINTER(SwAmrParams), ctypes.POINTER(SwAmrStats)]
     L.sw_cells.argtypes = [vp, vp, vp, vp]
+    L.sw_amr_plan.argtypes = [ctypes.POINTER(SwMeshDesc), vp, ctypes.POINTER(SwAmrParams), ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_int32), vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]
     L.sw_destroy.argtypes = [vp]
     L.sw_destroy.restype = None
     L.sw_last_error.restype = ctypes.c_char_p
@@ -182,6 +185,30 @@ def make_params(pd):
     p.tracer_decay = float(pd.get("tracer_decay", 0.0))
     p.quadrature = QUADRATURE[pd.get("quadrature", "subgrid")]
     return p
+
+
+def amr_plan(mesh, eta, indicator="vorticity", theta_r=1e-4, theta_c=5e-5, n_max=2, h_min=0.0):
+    """sw_amr_plan: the mesh decision of sw_remesh on the host.  Returns a dict
+    with the new leaves (level, i, j), the source kind (type) and cells (src
+    [n, 4]) of each, and the refine / merge counts."""
+    keep = []
+    md = make_mesh(mesh, keep)
+    e = np.ascontiguousarray(eta, dtype=np.float64)
+    ap = SwAmrParams(AMR_INDICATOR[indicator], float(theta_r), float(theta_c), int(n_max), float(h_min))
+    n = ctypes.c_int32(0)
+    nr, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    L = load()
+    st = L.sw_amr_plan(ctypes.byref(md), e.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ap), 0, ctypes.byref(n),
+                       None, None, None, None, None, ctypes.byref(nr), ctypes.byref(nc))
+    cap = n.value
+    out = {k: np.zeros(cap, dtype=np.int32) for k in ("level", "i", "j", "type")}
+    src = np.zeros((cap, 4), dtype=np.int32)
+    _check(L.sw_amr_plan(ctypes.byref(md), e.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ap), cap,
+                         ctypes.byref(n), *[out[k].ctypes.data_as(ctypes.c_void_p) for k in ("level", "i", "j", "type")],
+                         src.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nr), ctypes.byref(nc)), "sw_amr_plan")
+    del st
+    out.update(src=src, n_refined=nr.value, n_coarsened=nc.value)
+    return out
 
 
 def make_mesh(mesh, keep):

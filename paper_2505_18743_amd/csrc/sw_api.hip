@@ -275,6 +275,93 @@ struct LevelH {
   double* d_xv = nullptr;    // [nv] volume-rule node positions (SW_QUAD_PAPER)
 };
 
+// Device memory of contexts is recycled: a context hands its blocks to a
+// per-device cache when it is destroyed (its stream synchronised first), and
+// later contexts of that device take blocks from it before calling hipMalloc.
+// A remesh replaces a context by one of nearly the same size, so it then
+// allocates nothing.  Block sizes are rounded up to a multiple of 1/8 of
+// their power of two; the cache holds at most kCacheCap bytes per device.
+constexpr int kCacheDevices = 64;
+constexpr size_t kCacheCap = (size_t)4 << 30;
+std::mutex g_cache_mu;
+std::unordered_map<size_t, std::vector<void*>> g_cache[kCacheDevices];
+size_t g_cache_bytes[kCacheDevices] = {};
+
+size_t block_bytes(size_t n) {
+  if (n <= 256) return 256;
+  int e = 0;
+  while (((size_t)1 << e) < n) ++e;
+  const size_t q = (size_t)1 << (e > 3 ? e - 3 : 0);
+  return (n + q - 1) / q * q;
+}
+
+hipError_t cache_alloc(int dev, size_t bytes, void** p) {
+  if (dev >= 0 && dev < kCacheDevices) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto it = g_cache[dev].find(bytes);
+    if (it != g_cache[dev].end() && !it->second.empty()) {
+      *p = it->second.back();
+      it->second.pop_back();
+      g_cache_bytes[dev] -= bytes;
+      return hipSuccess;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
+// Host-to-device uploads of context set-up: the data are gathered into a
+// host blob, copied once into a pinned per-device staging buffer (held for
+// the process, guarded by a mutex until the copies have completed) and sent
+// with asynchronous copies on one stream.
+std::mutex g_stage_mu;
+void* g_stage[64] = {};
+size_t g_stage_bytes[64] = {};
+
+struct Uploads {
+  std::vector<char> blob;
+  std::vector<std::pair<void*, std::pair<size_t, size_t>>> item;   // dst, (offset, bytes)
+  void add(void* dst, const void* src, size_t bytes) {
+    const size_t off = (blob.size() + 255) / 256 * 256;
+    blob.resize(off + bytes);
+    if (bytes) std::memcpy(blob.data() + off, src, bytes);
+    item.push_back({dst, {off, bytes}});
+  }
+  // issues the copies and waits for them (the staging buffer is shared)
+  hipError_t flush(int dev, hipStream_t s) {
+    if (item.empty()) return hipSuccess;
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    const int d = dev >= 0 && dev < 64 ? dev : 0;
+    if (g_stage_bytes[d] < blob.size()) {
+      if (g_stage[d]) (void)hipHostFree(g_stage[d]);
+      g_stage[d] = nullptr;
+      g_stage_bytes[d] = 0;
+      hipError_t e = hipHostMalloc(&g_stage[d], blob.size(), hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      g_stage_bytes[d] = blob.size();
+    }
+    std::memcpy(g_stage[d], blob.data(), blob.size());
+    for (auto& it : item) {
+      if (!it.second.second) continue;
+      hipError_t e = hipMemcpyAsync(it.first, (char*)g_stage[d] + it.second.first, it.second.second,
+                                    hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(s);
+  }
+};
+
+void cache_free(int dev, void* p, size_t bytes) {
+  if (dev >= 0 && dev < kCacheDevices) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    if (g_cache_bytes[dev] + bytes <= kCacheCap) {
+      g_cache[dev][bytes].push_back(p);
+      g_cache_bytes[dev] += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 }  // namespace
 
 struct sw_ctx {
@@ -337,7 +424,7 @@ struct sw_ctx {
   bool bathy_set = false;
   int stage_done = 0;      // stages completed in the current step (0: no step open)
   int64_t nstep = 0;
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;   // device blocks and their sizes
   // kernel timing (sw_profile): events recorded around each launch group
   bool prof = false;
   int prof_mask = 0x7F;      // kernel classes timed while profiling
@@ -350,9 +437,10 @@ struct sw_ctx {
   sw_status alloc(T** p, size_t n) {
     void* q = nullptr;
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
-    if (e != hipSuccess) return fail(SW_ENOMEM, "hipMalloc failed for " + std::to_string(n * sizeof(T)) + " bytes");
-    allocs.push_back(q);
+    const size_t bytes = block_bytes(n * sizeof(T));
+    hipError_t e = cache_alloc(dev, bytes, &q);
+    if (e != hipSuccess) return fail(SW_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    allocs.push_back({q, bytes});
     *p = (T*)q;
     return SW_OK;
   }
@@ -365,7 +453,8 @@ struct sw_ctx {
       (void)hipEventDestroy(e.b);
     }
     ev.clear();
-    for (void* q : allocs) (void)hipFree(q);
+    if (!allocs.empty()) (void)hipStreamSynchronize(s);
+    for (auto& a : allocs) cache_free(dev, a.first, a.second);
     allocs.clear();
   }
   // Releases this context's device memory and events and takes over n's
@@ -473,6 +562,39 @@ void implicit_tableau(int rk, double At[4][4]) {
 
 int64_t key(int L, int i, int j) { return ((int64_t)L << 52) | ((int64_t)i << 26) | (int64_t)j; }
 
+// Cell lookup by (level, i, j): dense arrays for the levels below ndense
+// while their grids are small, a hash map for the other levels.  Values: a
+// cell index (>= 0) or another code of the caller's (<= -2); -1: none.
+class LeafIndex {
+ public:
+  LeafIndex(int nx0, int ny0, int nlev, int ndense) : nx0_(nx0), ny0_(ny0), nlev_(nlev) {
+    int64_t tot = 0;
+    ndense = std::min(ndense, nlev);
+    for (int L = 0; L < ndense; ++L) tot += ((int64_t)nx0 << L) * ((int64_t)ny0 << L);
+    ndense_ = tot <= ((int64_t)1 << 22) ? ndense : 0;
+    off_.assign(ndense_ + 1, 0);
+    for (int L = 0; L < ndense_; ++L) off_[L + 1] = off_[L] + ((int64_t)nx0 << L) * ((int64_t)ny0 << L);
+    grid_.assign((size_t)off_[ndense_], -1);
+  }
+  int get(int L, int i, int j) const {
+    if (L < 0 || L >= nlev_ || i < 0 || j < 0 || i >= (nx0_ << L) || j >= (ny0_ << L)) return -1;
+    if (L < ndense_) return grid_[(size_t)(off_[L] + (int64_t)j * (nx0_ << L) + i)];
+    auto it = map_.find(key(L, i, j));
+    return it == map_.end() ? -1 : it->second;
+  }
+  void set(int L, int i, int j, int v) {
+    if (L < ndense_) grid_[(size_t)(off_[L] + (int64_t)j * (nx0_ << L) + i)] = v;
+    else map_[key(L, i, j)] = v;
+  }
+
+ private:
+  int nx0_, ny0_, nlev_, ndense_ = 0;
+  std::vector<int64_t> off_;
+  std::vector<int> grid_;
+  std::unordered_map<int64_t, int> map_;
+};
+
+
 // Split [0, n) into chunks of at most `cap` items that do not cross a change of
 // member; chunks are listed member by member.  Output: chunk (begin, length)
 // pairs and the first chunk of every member (m0[M] = number of chunks).
@@ -497,7 +619,52 @@ void make_chunks(const std::vector<int>& mem_of, int M, int cap, std::vector<int
   m0[M] = (int)ch.size() / 2;
 }
 
+// Device tables depend only on (device, r, rule, S, volume rule): they are
+// built once per process and shared by every context (a remesh then builds
+// none); the cache owns them until the process ends.
+struct TabEntry {
+  std::vector<double> xh, wh, xv, wv;
+  double w1;
+  LevelTabs tabs, vtabs;
+  double *d_tab, *d_vtab, *d_xh, *d_xv;
+};
+std::mutex g_tab_mu;
+std::unordered_map<int64_t, TabEntry> g_tabs;
+
+template <class T>
+hipError_t tab_alloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max(n, (size_t)1) * sizeof(T));
+}
+
+sw_status build_tables_uncached(sw_ctx* c, LevelH& L);
+
 sw_status build_tables(sw_ctx* c, LevelH& L) {
+  const int64_t k = ((int64_t)c->dev << 40) | ((int64_t)c->r << 32) | ((int64_t)c->p.rule << 24) |
+                    ((int64_t)L.S << 8) | (int64_t)c->nv;
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  auto it = g_tabs.find(k);
+  if (it == g_tabs.end()) {
+    sw_status st = build_tables_uncached(c, L);
+    if (st != SW_OK) return st;
+    g_tabs[k] = TabEntry{L.xh, L.wh, L.xv, L.wv, L.w1, L.tabs, L.vtabs, L.d_tab, L.d_vtab, L.d_xh, L.d_xv};
+    return SW_OK;
+  }
+  const TabEntry& e = it->second;
+  L.xh = e.xh;
+  L.wh = e.wh;
+  L.xv = e.xv;
+  L.wv = e.wv;
+  L.w1 = e.w1;
+  L.tabs = e.tabs;
+  L.vtabs = e.vtabs;
+  L.d_tab = e.d_tab;
+  L.d_vtab = e.d_vtab;
+  L.d_xh = e.d_xh;
+  L.d_xv = e.d_xv;
+  return SW_OK;
+}
+
+sw_status build_tables_uncached(sw_ctx* c, LevelH& L) {
   const int S = L.S, N1 = c->N1, NP = c->NP;
   if (c->p.rule == SW_RULE_EQ) eqr(S, L.xh, L.wh);
   else gll(S, L.xh, L.wh);
@@ -558,8 +725,8 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
     tab[o_mq + i] = Mq[i];
   }
   for (int j = 0; j < NP; ++j) tab[o_mean + j] = mean[j];
-  sw_status st = c->alloc(&L.d_tab, total);
-  if (st != SW_OK) return st;
+  sw_status st = SW_OK;
+  HIPCHK(tab_alloc(&L.d_tab, total));
   HIPCHK(hipMemcpy(L.d_tab, tab.data(), total * sizeof(double), hipMemcpyHostToDevice));
   L.tabs.w = L.d_tab + o_w;
   L.tabs.l = L.d_tab + o_l;
@@ -574,8 +741,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
   L.tabs.S = S;
   L.w1 = L.wh[0];
   L.vtabs = L.tabs;
-  st = c->alloc(&L.d_xh, (size_t)S);
-  if (st != SW_OK) return st;
+  HIPCHK(tab_alloc(&L.d_xh, (size_t)S));
   HIPCHK(hipMemcpy(L.d_xh, L.xh.data(), S * sizeof(double), hipMemcpyHostToDevice));
   if (c->nv > 0) {
     // the volume terms' Gauss-Legendre rule (Table 1): weights, basis values
@@ -595,8 +761,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
         vt[v_wd + a * N1 + k] = L.wv[a] * dlag(xi, k, L.xv[a]);
       }
     }
-    st = c->alloc(&L.d_vtab, vtotal);
-    if (st != SW_OK) return st;
+    HIPCHK(tab_alloc(&L.d_vtab, vtotal));
     HIPCHK(hipMemcpy(L.d_vtab, vt.data(), vtotal * sizeof(double), hipMemcpyHostToDevice));
     L.vtabs.w = L.d_vtab + v_w;
     L.vtabs.l = L.d_vtab + v_l;
@@ -605,8 +770,7 @@ sw_status build_tables(sw_ctx* c, LevelH& L) {
     L.vtabs.wd = L.d_vtab + v_wd;
     L.vtabs.fl = nullptr;
     L.vtabs.S = nv;
-    st = c->alloc(&L.d_xv, (size_t)nv);
-    if (st != SW_OK) return st;
+    HIPCHK(tab_alloc(&L.d_xv, (size_t)nv));
     HIPCHK(hipMemcpy(L.d_xv, L.xv.data(), nv * sizeof(double), hipMemcpyHostToDevice));
   }
   return SW_OK;
@@ -1004,7 +1168,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   // per-member validation: level order, extent, tiling, duplicates
   int maxL = 0;
   int64_t Ktot = 0;
-  std::vector<std::unordered_map<int64_t, int>> leaf(M);
+  std::vector<LeafIndex> leaf;
+  leaf.reserve(M);
   for (int m = 0; m < M; ++m) {
     const sw_mesh_desc& md = meshes[m];
     c->mx0.push_back(md.x0);
@@ -1014,7 +1179,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     c->mny0.push_back(md.ny0);
     c->mbc.push_back({md.bc[0], md.bc[1], md.bc[2], md.bc[3]});
     long double area = 0.0L;
-    leaf[m].reserve((size_t)md.n_cells * 2);
+    if (md.nx0 < 1 || md.ny0 < 1) return bail(SW_EINVAL, "bad coarse grid");
+    leaf.emplace_back(md.nx0, md.ny0, p->n_levels, p->n_levels);
     for (int k = 0; k < md.n_cells; ++k) {
       const int L = md.level[k];
       if (L < 0 || L >= p->n_levels) return bail(SW_EINVAL, "cell level out of range (n_levels)");
@@ -1023,7 +1189,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
         return bail(SW_EINVAL, "cell outside the domain");
       maxL = std::max(maxL, L);
       area += std::ldexp(1.0L, -2 * L);
-      if (!leaf[m].emplace(key(L, md.i[k], md.j[k]), k).second) return bail(SW_EINVAL, "duplicate cell");
+      if (leaf[m].get(L, md.i[k], md.j[k]) != -1) return bail(SW_EINVAL, "duplicate cell");
+      leaf[m].set(L, md.i[k], md.j[k], k);
     }
     if (std::fabs((double)(area - (long double)md.nx0 * md.ny0)) > 1e-9)
       return bail(SW_EINVAL, "cells do not tile the domain");
@@ -1098,16 +1265,16 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
         fh.push_back({k, -1, sd, 0, -1, 1, md.bc[sd], L});
         continue;
       }
-      auto it = leaf[m].find(key(L, ni, nj));
-      if (it != leaf[m].end()) {
-        if (sd == 1 || sd == 3) fh.push_back({k, ctx_of[m][it->second], sd, opp[sd], -1, 0, 0, L});
+      const int it = leaf[m].get(L, ni, nj);
+      if (it >= 0) {
+        if (sd == 1 || sd == 3) fh.push_back({k, ctx_of[m][it], sd, opp[sd], -1, 0, 0, L});
         continue;
       }
       if (L > 0) {
-        auto ic = leaf[m].find(key(L - 1, ni >> 1, nj >> 1));
-        if (ic != leaf[m].end()) {
+        const int ic = leaf[m].get(L - 1, ni >> 1, nj >> 1);
+        if (ic >= 0) {
           const int sub = (sd < 2) ? (j & 1) : (i & 1);
-          fh.push_back({k, ctx_of[m][ic->second], sd, opp[sd], sub, 0, 0, L});
+          fh.push_back({k, ctx_of[m][ic], sd, opp[sd], sub, 0, 0, L});
           continue;
         }
       }
@@ -1122,7 +1289,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
           ki = 2 * ni + t;
           kj = 2 * nj + (sd == 2 ? 1 : 0);
         }
-        if (leaf[m].find(key(L + 1, ki, kj)) == leaf[m].end()) ok = false;
+        if (leaf[m].get(L + 1, ki, kj) < 0) ok = false;
       }
       if (!ok)
         return bail(SW_EINVAL, "mesh is not 2:1 balanced at cell " + std::to_string(c->cloc[k]) + " of member " +
@@ -1132,9 +1299,15 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   // class of a face: x or y direction times (conforming/boundary, sub-face 0, sub-face 1);
   // the stable sort keeps the faces of a class grouped by member
   auto cls = [](const FaceH& h) { return (h.sa < 2 ? 0 : 3) + (h.sub + 1); };
-  std::stable_sort(fh.begin(), fh.end(), [&](const FaceH& x, const FaceH& y) {
-    return x.lvl != y.lvl ? x.lvl < y.lvl : cls(x) < cls(y);
-  });
+  {   // counting sort by (level, class), stable
+    const int nb = 6 * (int)c->lv.size();
+    std::vector<int> cnt(nb + 1, 0);
+    for (const FaceH& h : fh) ++cnt[6 * h.lvl + cls(h) + 1];
+    for (int b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+    std::vector<FaceH> sorted(fh.size());
+    for (const FaceH& h : fh) sorted[cnt[6 * h.lvl + cls(h)]++] = h;
+    fh.swap(sorted);
+  }
   c->F = (int)fh.size();
   std::vector<int> fA(c->F), fB(c->F), meta(c->F), used((size_t)K * 8, 0), fmem(c->F);
   for (int f = 0; f < c->F; ++f) {
@@ -1243,8 +1416,8 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
       delete c;
       return st;
     }
-    hipError_t e = hipMemset(L.d_wflag, 0, (size_t)std::max(L.nblk, 1));
-    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    hipError_t e = hipMemsetAsync(L.d_wflag, 0, (size_t)std::max(L.nblk, 1), c->s);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   }
   std::vector<double> cw1(K), mtide(4 * (size_t)M), mcfl(M);
   for (int k = 0; k < K; ++k) cw1[k] = p->cfl_mode == 1 ? c->lv[c->lev[k]].w1 : 1.0;
@@ -1255,15 +1428,14 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     mtide[4 * m + 3] = params[m].tide_c_in;
     mcfl[m] = params[m].cfl;
   }
-#define H2D(dst, src, n)                                                                       \
-  do {                                                                                         \
-    hipError_t e_ = hipMemcpy(dst, src, (n) * sizeof(*(src)), hipMemcpyHostToDevice);          \
-    if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e_)); \
-  } while (0)
+  // host data goes to the device through one pinned staging buffer with
+  // asynchronous copies on the context's stream, awaited at the end
+  Uploads up;
+#define H2D(dst, src, n) up.add((void*)(dst), (const void*)(src), (size_t)(n) * sizeof(*(src)))
 #define ZERO(dst, bytes)                                                                       \
   do {                                                                                         \
-    hipError_t e_ = hipMemset(dst, 0, bytes);                                                  \
-    if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e_)); \
+    hipError_t e_ = hipMemsetAsync(dst, 0, bytes, c->s);                                       \
+    if (e_ != hipSuccess) return bail(SW_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e_)); \
   } while (0)
   {
     // node offsets of the faces with given boundary data (S nodes of the face's level)
@@ -1338,9 +1510,10 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   ZERO(c->d_hn, sizeof(double) * K * c->NP);
   ZERO(c->d_cn, sizeof(double) * K * c->NP);
   {
-    hipError_t e = hipMemset(c->d_flag, c->r, K);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    hipError_t e = hipMemsetAsync(c->d_flag, c->r, K, c->s);
+    if (e == hipSuccess) e = up.flush(c->dev, c->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("context set-up: ") + hipGetErrorString(e));
   }
 #undef H2D
 #undef ZERO
@@ -1814,11 +1987,19 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
 // ---------------------------------------------------------------------------
 namespace {
 
-// Device buffer freed at scope exit (the call synchronises its stream first).
+// Device buffer from the block cache, returned at scope exit (the call has
+// synchronised its stream by then).
 struct TmpBuf {
+  int dev;
   void* p = nullptr;
+  size_t bytes = 0;
+  explicit TmpBuf(int d) : dev(d) {}
+  hipError_t get(size_t n) {
+    bytes = block_bytes(n);
+    return cache_alloc(dev, bytes, &p);
+  }
   ~TmpBuf() {
-    if (p) (void)hipFree(p);
+    if (p) cache_free(dev, p, bytes);
   }
 };
 
@@ -1887,8 +2068,8 @@ sw_status amr_eta(sw_ctx* c, int kind, double* eta) {
 // Total mass sum_K int h and sum_K int z_b l of the current state on the
 // sample rule (synchronises).
 sw_status amr_mass(sw_ctx* c, double& mass, double& bathy) {
-  TmpBuf b;
-  HIPCHK(hipMalloc(&b.p, sizeof(double) * (2 * (size_t)c->K + 2)));
+  TmpBuf b(c->dev);
+  HIPCHK(b.get(sizeof(double) * (2 * (size_t)c->K + 2)));
   double* v = (double*)b.p;
   for (auto& L : c->lv) {
     AmrMassArgs a{};
@@ -1930,13 +2111,24 @@ struct AmrPlan {
   int64_t n_refined = 0, n_coarsened = 0;
 };
 
-AmrPlan amr_plan(const sw_ctx* c, const std::vector<double>& eta, double eta_max, const sw_amr_params& ap) {
-  const int K = c->K;
-  const int nx0 = c->mnx0[0], ny0 = c->mny0[0];
-  const bool perx = c->mbc[0][0] == SW_BC_PERIODIC, pery = c->mbc[0][2] == SW_BC_PERIODIC;
-  auto kL = [](int64_t k) { return (int)(k >> 52); };
-  auto ki = [](int64_t k) { return (int)((k >> 26) & ((1 << 26) - 1)); };
-  auto kj = [](int64_t k) { return (int)(k & ((1 << 26) - 1)); };
+// One member's leaves (cells sorted by level) and their indicator values.
+struct PlanInput {
+  int K, nx0, ny0;
+  bool perx, pery;
+  const int *lev, *ci, *cj;
+  const double* cdx;
+  const double* eta;
+};
+
+AmrPlan amr_plan(const PlanInput& in, double eta_max, const sw_amr_params& ap) {
+  struct {
+    const int *lev, *ci, *cj;
+    const double* cdx;
+  } cc{in.lev, in.ci, in.cj, in.cdx}, *c = &cc;
+  const int K = in.K;
+  const int nx0 = in.nx0, ny0 = in.ny0;
+  const bool perx = in.perx, pery = in.pery;
+  const double* eta = in.eta;
   // face neighbour position at level L (periodic sides wrap); false outside
   auto neighbour = [&](int L, int i, int j, int di, int dj, int& ni, int& nj) {
     const int nxL = nx0 << L, nyL = ny0 << L;
@@ -1952,74 +2144,71 @@ AmrPlan amr_plan(const sw_ctx* c, const std::vector<double>& eta, double eta_max
     }
     return true;
   };
-  std::vector<char> refine(K), coarsen(K);
+  int maxL = 0;
+  for (int k = 0; k < K; ++k) maxL = std::max(maxL, c->lev[k]);
+  // levels up to maxL + 1 are looked up (children of refined cells, the cells
+  // two levels below a merged parent); the new ones are few and hashed
+  LeafIndex idx(nx0, ny0, std::max(maxL + 2, ap.n_max), maxL + 1);
+  for (int k = 0; k < K; ++k) idx.set(c->lev[k], c->ci[k], c->cj[k], k);
+  std::vector<char> refine(K), coarsen(K), gone(K, 0);
   for (int k = 0; k < K; ++k) {
-    const double dx = c->cdx[k];
-    refine[k] = eta[k] > ap.theta_r * eta_max && c->lev[k] + 1 < ap.n_max && dx > ap.h_min;
+    refine[k] = eta[k] > ap.theta_r * eta_max && c->lev[k] + 1 < ap.n_max && c->cdx[k] > ap.h_min;
     coarsen[k] = eta[k] < ap.theta_c * eta_max && c->lev[k] > 0 && !refine[k];
   }
-  std::unordered_map<int64_t, int> old;
-  old.reserve((size_t)K * 2);
-  for (int k = 0; k < K; ++k) old.emplace(key(c->lev[k], c->ci[k], c->cj[k]), k);
-  std::unordered_set<int64_t> leaves;
-  leaves.reserve((size_t)K * 4);
-  auto split = [&](int64_t k) {
-    leaves.erase(k);
-    const int L = kL(k), i = ki(k), j = kj(k);
-    for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a) leaves.insert(key(L + 1, 2 * i + a, 2 * j + b));
+  struct Added { int L, i, j; char gone; };
+  std::vector<Added> added;
+  auto is_leaf = [&](int L, int i, int j) {
+    const int v = idx.get(L, i, j);
+    return v >= 0 ? !gone[v] : (v <= -2 ? !added[-2 - v].gone : false);
   };
-  for (int k = 0; k < K; ++k) {
-    const int64_t kk = key(c->lev[k], c->ci[k], c->cj[k]);
-    if (refine[k]) {
-      leaves.insert(kk);
-      split(kk);
-    } else {
-      leaves.insert(kk);
-    }
-  }
-  // 2:1 balance across faces: refine every leaf two or more levels coarser
-  // than a face neighbour, until none is left
-  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-  for (bool changed = true; changed;) {
-    changed = false;
-    std::vector<int64_t> cur(leaves.begin(), leaves.end());
-    std::sort(cur.begin(), cur.end());
-    for (int64_t kk : cur) {
-      if (!leaves.count(kk)) continue;
-      const int L = kL(kk), i = ki(kk), j = kj(kk);
-      for (int sd = 0; sd < 4; ++sd) {
-        int ni, nj;
-        if (!neighbour(L, i, j, di[sd], dj[sd], ni, nj)) continue;
-        for (int A = L - 2; A >= 0; --A) {
-          const int64_t ck = key(A, ni >> (L - A), nj >> (L - A));
-          if (leaves.count(ck)) {
-            split(ck);
-            changed = true;
-            break;
-          }
-        }
+  std::vector<int> queue;   // added leaves whose faces are still to check
+  auto split = [&](int L, int i, int j) {
+    const int v = idx.get(L, i, j);
+    if (v >= 0) gone[v] = 1;
+    else added[-2 - v].gone = 1;
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        added.push_back({L + 1, 2 * i + a, 2 * j + b, 0});
+        idx.set(L + 1, 2 * i + a, 2 * j + b, -2 - (int)(added.size() - 1));
+        queue.push_back((int)added.size() - 1);
       }
+  };
+  for (int k = 0; k < K; ++k)
+    if (refine[k]) split(c->lev[k], c->ci[k], c->cj[k]);
+  // 2:1 balance across faces: a new leaf that faces a leaf two or more levels
+  // coarser has that leaf refined (only new, finer leaves can create such a
+  // pair, so checking each new leaf once reaches the fixed point)
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  for (size_t q = 0; q < queue.size(); ++q) {
+    const Added e = added[queue[q]];
+    if (e.gone) continue;
+    for (int sd = 0; sd < 4; ++sd) {
+      int ni, nj;
+      if (!neighbour(e.L, e.i, e.j, di[sd], dj[sd], ni, nj)) continue;
+      for (int A = e.L - 2; A >= 0; --A)
+        if (is_leaf(A, ni >> (e.L - A), nj >> (e.L - A))) {
+          split(A, ni >> (e.L - A), nj >> (e.L - A));
+          break;
+        }
     }
   }
   AmrPlan P;
-  for (auto& kv : old)
-    if (!leaves.count(kv.first)) ++P.n_refined;
-  // merges of four flagged sibling leaves that keep the balance
+  for (int k = 0; k < K; ++k) P.n_refined += gone[k];
+  // merges of four flagged sibling leaves that keep the balance (decided on
+  // the mesh before any merge)
   std::vector<int64_t> parents;
   for (int k = 0; k < K; ++k)
-    if (coarsen[k]) parents.push_back(key(c->lev[k] - 1, c->ci[k] >> 1, c->cj[k] >> 1));
+    if (coarsen[k] && !gone[k]) parents.push_back(key(c->lev[k] - 1, c->ci[k] >> 1, c->cj[k] >> 1));
   std::sort(parents.begin(), parents.end());
   parents.erase(std::unique(parents.begin(), parents.end()), parents.end());
-  std::vector<int64_t> merged;
+  std::vector<std::array<int, 3>> merged;
   for (int64_t pk : parents) {
-    const int L = kL(pk), pi = ki(pk), pj = kj(pk);
+    const int L = (int)(pk >> 52), pi = (int)((pk >> 26) & ((1 << 26) - 1)), pj = (int)(pk & ((1 << 26) - 1));
     bool ok = true;
     for (int b = 0; b < 2 && ok; ++b)
       for (int a = 0; a < 2 && ok; ++a) {
-        const int64_t kd = key(L + 1, 2 * pi + a, 2 * pj + b);
-        auto it = old.find(kd);
-        ok = it != old.end() && leaves.count(kd) && coarsen[it->second];
+        const int v = idx.get(L + 1, 2 * pi + a, 2 * pj + b);
+        ok = v >= 0 && !gone[v] && coarsen[v];
       }
     for (int sd = 0; sd < 4 && ok; ++sd) {
       int ni, nj;
@@ -2030,44 +2219,77 @@ AmrPlan amr_plan(const sw_ctx* c, const std::vector<double>& eta, double eta_max
         else if (sd == 1) ci = 4 * ni, cj = 4 * nj + t;
         else if (sd == 2) ci = 4 * ni + t, cj = 4 * nj + 3;
         else ci = 4 * ni + t, cj = 4 * nj;
-        if (leaves.count(key(L + 2, ci, cj))) ok = false;
+        if (is_leaf(L + 2, ci, cj)) ok = false;
       }
     }
-    if (ok) merged.push_back(pk);
+    if (ok) merged.push_back({L, pi, pj});
   }
-  for (int64_t pk : merged) {
-    const int L = kL(pk), pi = ki(pk), pj = kj(pk);
+  for (auto& m : merged) {
     for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a) leaves.erase(key(L + 1, 2 * pi + a, 2 * pj + b));
-    leaves.insert(pk);
+      for (int a = 0; a < 2; ++a) gone[idx.get(m[0] + 1, 2 * m[1] + a, 2 * m[2] + b)] = 1;
+    added.push_back({m[0], m[1], m[2], 0});   // (not entered in idx: no later lookups of it)
   }
   P.n_coarsened = (int64_t)merged.size();
-  std::vector<std::array<int, 3>> nl;
-  nl.reserve(leaves.size());
-  for (int64_t kk : leaves) nl.push_back({kL(kk), kj(kk), ki(kk)});
-  std::sort(nl.begin(), nl.end());
-  for (auto& e : nl) {
-    const int L = e[0], j = e[1], i = e[2];
-    P.lev.push_back(L);
-    P.ci.push_back(i);
-    P.cj.push_back(j);
-    auto it = old.find(key(L, i, j));
-    if (it != old.end()) {
-      P.type.push_back(0);
-      P.src.insert(P.src.end(), {it->second, 0, 0, 0});
-      continue;
+  // new leaves in (level, j, i) order: the kept old cells (in their order when
+  // that order is already sorted) merged with the sorted new ones
+  auto order = [](int L, int j, int i) { return ((int64_t)L << 52) | ((int64_t)j << 26) | (int64_t)i; };
+  bool sorted = true;
+  for (int k = 1; k < K && sorted; ++k)
+    sorted = order(c->lev[k - 1], c->cj[k - 1], c->ci[k - 1]) < order(c->lev[k], c->cj[k], c->ci[k]);
+  std::vector<std::pair<int64_t, int>> newl;   // (order key, old index or -2 - added index)
+  for (size_t a = 0; a < added.size(); ++a)
+    if (!added[a].gone) newl.push_back({order(added[a].L, added[a].j, added[a].i), -2 - (int)a});
+  std::sort(newl.begin(), newl.end());
+  std::vector<std::pair<int64_t, int>> all;
+  all.reserve((size_t)K + newl.size());
+  if (sorted) {
+    size_t q = 0;
+    for (int k = 0; k < K; ++k) {
+      if (gone[k]) continue;
+      const int64_t ok = order(c->lev[k], c->cj[k], c->ci[k]);
+      while (q < newl.size() && newl[q].first < ok) all.push_back(newl[q++]);
+      all.push_back({ok, k});
     }
-    if (L > 0 && (it = old.find(key(L - 1, i >> 1, j >> 1))) != old.end()) {
-      P.type.push_back(1);
-      P.src.insert(P.src.end(), {it->second, 2 * (j & 1) + (i & 1), 0, 0});
-      continue;
-    }
-    P.type.push_back(2);
-    for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a) {
-        auto kd = old.find(key(L + 1, 2 * i + a, 2 * j + b));
-        P.src.push_back(kd == old.end() ? -1 : kd->second);
+    while (q < newl.size()) all.push_back(newl[q++]);
+  } else {
+    for (int k = 0; k < K; ++k)
+      if (!gone[k]) all.push_back({order(c->lev[k], c->cj[k], c->ci[k]), k});
+    all.insert(all.end(), newl.begin(), newl.end());
+    std::sort(all.begin(), all.end());
+  }
+  const size_t Kn = all.size();
+  P.lev.resize(Kn);
+  P.ci.resize(Kn);
+  P.cj.resize(Kn);
+  P.type.resize(Kn);
+  P.src.assign(4 * Kn, 0);
+  for (size_t n = 0; n < Kn; ++n) {
+    const int v = all[n].second;
+    int L, i, j;
+    if (v >= 0) {
+      L = c->lev[v], i = c->ci[v], j = c->cj[v];
+      P.type[n] = 0;
+      P.src[4 * n] = v;
+    } else {
+      const Added& e = added[-2 - v];
+      L = e.L, i = e.i, j = e.j;
+      const int par = L > 0 ? idx.get(L - 1, i >> 1, j >> 1) : -1;
+      if (par >= 0 && gone[par]) {   // a child of a refined old cell
+        P.type[n] = 1;
+        P.src[4 * n] = par;
+        P.src[4 * n + 1] = 2 * (j & 1) + (i & 1);
+      } else {                       // a parent of four old cells
+        P.type[n] = 2;
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a) {
+            const int kd = idx.get(L + 1, 2 * i + a, 2 * j + b);
+            P.src[4 * n + 2 * b + a] = kd >= 0 ? kd : -1;
+          }
       }
+    }
+    P.lev[n] = L;
+    P.ci[n] = i;
+    P.cj[n] = j;
   }
   return P;
 }
@@ -2132,6 +2354,46 @@ sw_status amr_common_checks(sw_ctx* c) {
 
 extern "C" {
 
+sw_status sw_amr_plan(const sw_mesh_desc* mesh, const double* eta, const sw_amr_params* ap, int32_t cap,
+                      int32_t* n_new, int32_t* level, int32_t* i, int32_t* j, int32_t* type, int32_t* src,
+                      int64_t* n_refined, int64_t* n_coarsened) {
+  if (!mesh || !eta || !ap || !n_new) return fail(SW_EINVAL, "NULL argument to sw_amr_plan");
+  const int K = mesh->n_cells;
+  if (K < 1 || !mesh->level || !mesh->i || !mesh->j || mesh->nx0 < 1 || mesh->ny0 < 1 || !(mesh->dx0 > 0.0))
+    return fail(SW_EINVAL, "bad mesh");
+  if (ap->n_max < 1 || ap->n_max > 24) return fail(SW_EINVAL, "n_max must be 1 .. 24");
+  std::vector<double> cdx(K);
+  std::unordered_set<int64_t> seen;
+  seen.reserve((size_t)K * 2);
+  for (int k = 0; k < K; ++k) {
+    const int L = mesh->level[k];
+    if (L < 0 || L > 24 || mesh->i[k] < 0 || mesh->j[k] < 0 || mesh->i[k] >= (mesh->nx0 << L) ||
+        mesh->j[k] >= (mesh->ny0 << L))
+      return fail(SW_EINVAL, "cell outside the domain");
+    if (!seen.insert(key(L, mesh->i[k], mesh->j[k])).second) return fail(SW_EINVAL, "duplicate cell");
+    cdx[k] = mesh->dx0 / std::ldexp(1.0, L);
+  }
+  double eta_max = 0.0;
+  for (int k = 0; k < K; ++k) eta_max = std::max(eta_max, eta[k]);
+  PlanInput pin{K, mesh->nx0, mesh->ny0, mesh->bc[0] == SW_BC_PERIODIC, mesh->bc[2] == SW_BC_PERIODIC,
+                mesh->level, mesh->i, mesh->j, cdx.data(), eta};
+  AmrPlan P = amr_plan(pin, eta_max, *ap);
+  const int Kn = (int)P.lev.size();
+  *n_new = Kn;
+  if (n_refined) *n_refined = P.n_refined;
+  if (n_coarsened) *n_coarsened = P.n_coarsened;
+  if (cap < Kn) return fail(SW_EINVAL, "sw_amr_plan: the new mesh has " + std::to_string(Kn) + " cells, more than cap");
+  for (int n = 0; n < Kn; ++n) {
+    if (level) level[n] = P.lev[n];
+    if (i) i[n] = P.ci[n];
+    if (j) j[n] = P.cj[n];
+    if (type) type[n] = P.type[n];
+    if (src)
+      for (int q = 0; q < 4; ++q) src[4 * n + q] = P.src[4 * n + q];
+  }
+  return SW_OK;
+}
+
 sw_status sw_cells(const sw_ctx* c, int32_t* level, int32_t* i, int32_t* j) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   for (int k = 0; k < c->K; ++k) {
@@ -2155,9 +2417,12 @@ sw_status sw_set_bed_grid(sw_ctx* c, int32_t nx, int32_t ny, double x0, double y
   if (!c->d_grid || (size_t)c->gnx * c->gny != n) {
     if (c->d_grid) {   // the previous raster's memory
       HIPCHK(hipStreamSynchronize(c->s));
-      auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_grid);
-      if (it != c->allocs.end()) c->allocs.erase(it);
-      HIPCHK(hipFree(c->d_grid));
+      auto it = std::find_if(c->allocs.begin(), c->allocs.end(),
+                             [&](const std::pair<void*, size_t>& a) { return a.first == (void*)c->d_grid; });
+      if (it != c->allocs.end()) {
+        cache_free(c->dev, it->first, it->second);
+        c->allocs.erase(it);
+      }
       c->d_grid = nullptr;
     }
     sw_status st = c->alloc(&c->d_grid, n);
@@ -2201,8 +2466,8 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
   const int K = c->K;
   std::vector<double> eta(K);
   {
-    TmpBuf b;
-    HIPCHK(hipMalloc(&b.p, sizeof(double) * (size_t)std::max(K, 1)));
+    TmpBuf b(c->dev);
+    HIPCHK(b.get(sizeof(double) * (size_t)std::max(K, 1)));
     if ((st = amr_eta(c, ap->indicator, (double*)b.p)) != SW_OK) return st;
     HIPCHK(hipMemcpyAsync(eta.data(), b.p, sizeof(double) * K, hipMemcpyDeviceToHost, c->s));
     HIPCHK(hipStreamSynchronize(c->s));
@@ -2214,7 +2479,9 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
   S.eta_max = eta_max;
   if ((st = amr_mass(c, S.mass_old, S.q_bathy)) != SW_OK) return st;
   const double bathy_old = S.q_bathy;
-  AmrPlan P = amr_plan(c, eta, eta_max, *ap);
+  PlanInput pin{K, c->mnx0[0], c->mny0[0], c->mbc[0][0] == SW_BC_PERIODIC, c->mbc[0][2] == SW_BC_PERIODIC,
+                c->lev.data(), c->ci.data(), c->cj.data(), c->cdx.data(), eta.data()};
+  AmrPlan P = amr_plan(pin, eta_max, *ap);
   S.n_refined = P.n_refined;
   S.n_coarsened = P.n_coarsened;
   S.n_cells_new = (int64_t)P.lev.size();
@@ -2224,8 +2491,8 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
     if (out) *out = S;
     return SW_OK;
   }
-  for (int v : P.src)
-    if (v < 0) return fail(SW_EINVAL, "sw_remesh: a new cell has no source cell");
+  for (size_t q = 0; q < P.src.size(); ++q)
+    if (P.src[q] < 0) return fail(SW_EINVAL, "sw_remesh: a new cell has no source cell");
   std::vector<double> tchild, tproj;
   if (!transfer_tables(c->r, tchild, tproj)) return fail(SW_EINVAL, "sw_remesh: mass matrix not SPD");
   // the context of the new mesh, on the same stream with the same parameters
@@ -2248,7 +2515,7 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
     return e;
   };
   const int Kn = n->K, NP = c->NP;
-  TmpBuf bt, bs, btab;
+  TmpBuf bt(c->dev), bs(c->dev), btab(c->dev);
   auto d2d = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->s);
   };
@@ -2261,9 +2528,9 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
   if (e == hipSuccess) e = d2d(n->d_mdiag, c->d_mdiag, kMDiag * sizeof(double));
   if (e == hipSuccess && n->alloc(&n->d_grid, (size_t)c->gnx * c->gny) != SW_OK) e = hipErrorOutOfMemory;
   if (e == hipSuccess) e = d2d(n->d_grid, c->d_grid, sizeof(double) * (size_t)c->gnx * c->gny);
-  if (e == hipSuccess) e = hipMalloc(&bt.p, sizeof(int) * (size_t)Kn);
-  if (e == hipSuccess) e = hipMalloc(&bs.p, sizeof(int) * 4 * (size_t)Kn);
-  if (e == hipSuccess) e = hipMalloc(&btab.p, sizeof(double) * 8 * (size_t)NP * NP);
+  if (e == hipSuccess) e = bt.get(sizeof(int) * (size_t)Kn);
+  if (e == hipSuccess) e = bs.get(sizeof(int) * 4 * (size_t)Kn);
+  if (e == hipSuccess) e = btab.get(sizeof(double) * 8 * (size_t)NP * NP);
   if (e == hipSuccess) e = hipMemcpyAsync(bt.p, P.type.data(), sizeof(int) * Kn, hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipMemcpyAsync(bs.p, P.src.data(), sizeof(int) * 4 * Kn, hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess)
