@@ -868,6 +868,8 @@ def main():
     if not args.no_vortex:
         progress("vortex")
         line["vortex"] = vortex_bench(dev)
+    if not args.no_vortex_amr:
+        line["vortex_amr"] = vortex_amr_bench(dev)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host)")
         line["cpu_baseline"] = cpu_baseline(args.workload)

@@ -1178,7 +1178,9 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     c->mnx0.push_back(md.nx0);
     c->mny0.push_back(md.ny0);
     c->mbc.push_back({md.bc[0], md.bc[1], md.bc[2], md.bc[3]});
-    long double area = 0.0L;
+    // area in units of the finest level's cells (exact in integers)
+    const int sh = 2 * (p->n_levels - 1);
+    int64_t area = 0;
     if (md.nx0 < 1 || md.ny0 < 1) return bail(SW_EINVAL, "bad coarse grid");
     leaf.emplace_back(md.nx0, md.ny0, p->n_levels, p->n_levels);
     for (int k = 0; k < md.n_cells; ++k) {
@@ -1188,12 +1190,11 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
       if (md.i[k] < 0 || md.j[k] < 0 || md.i[k] >= (md.nx0 << L) || md.j[k] >= (md.ny0 << L))
         return bail(SW_EINVAL, "cell outside the domain");
       maxL = std::max(maxL, L);
-      area += std::ldexp(1.0L, -2 * L);
+      area += (int64_t)1 << (sh - 2 * L);
       if (leaf[m].get(L, md.i[k], md.j[k]) != -1) return bail(SW_EINVAL, "duplicate cell");
       leaf[m].set(L, md.i[k], md.j[k], k);
     }
-    if (std::fabs((double)(area - (long double)md.nx0 * md.ny0)) > 1e-9)
-      return bail(SW_EINVAL, "cells do not tile the domain");
+    if (area != ((int64_t)md.nx0 * md.ny0) << sh) return bail(SW_EINVAL, "cells do not tile the domain");
     Ktot += md.n_cells;
   }
   if (Ktot > (int64_t)1 << 30) return bail(SW_EINVAL, "too many cells");
@@ -1243,6 +1244,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   // boundary; A is the fine or equal side.  Faces join cells of one member only.
   struct FaceH { int a, b, sa, sb, sub, bnd, bc, lvl; };
   std::vector<FaceH> fh;
+  fh.reserve((size_t)K * 3);
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1}, opp[4] = {1, 0, 3, 2};
   for (int k = 0; k < K; ++k) {
     const int m = c->cmem[k];
