@@ -318,6 +318,8 @@ typedef struct {
   double q_bathy;            /* Q^n of eq:mass-loss: sum_K int z_b l over the new  */
                              /* cells minus the same over the old cells, l the     */
                              /* land-sea mask of the state on each mesh           */
+  int32_t boundary_data_kept;/* 1: the given data of state and discharge sides   */
+                             /* carried over (their faces are unchanged)          */
 } sw_amr_stats;
 
 /* Bathymetry raster: bed ELEVATION b_dev[j][i] (device, nx x ny, nx, ny >= 2)
@@ -345,7 +347,9 @@ sw_status sw_amr_indicator(sw_ctx *c, int32_t indicator, double *eta_dev);
  * column i (sw_cells lists them); every cell starts at degree r; the
  * bathymetry of all cells is sampled from the raster of sw_set_bed_grid
  * (SW_EINVAL without one).  Time, time step, tide and CFL number carry over;
- * the boundary data of state and discharge sides must be given again
+ * the boundary data of state and discharge sides carry over when the
+ * faces that take them are unchanged (same cells and sides in the same
+ * order; out->boundary_data_kept = 1) and must be given again otherwise
  * (sw_set_boundary_state), and the per-launch-shape choices of
  * sw_set_workgroup / sw_autotune return to their defaults.  All arrays sized
  * by the mesh change with it (sw_counts).  out (may be NULL) receives the

@@ -58,7 +58,7 @@ class SwAmrParams(ctypes.Structure):
 class SwAmrStats(ctypes.Structure):
     _fields_ = [("n_cells_old", ctypes.c_int64), ("n_cells_new", ctypes.c_int64), ("n_refined", ctypes.c_int64),
                 ("n_coarsened", ctypes.c_int64), ("eta_max", ctypes.c_double), ("mass_old", ctypes.c_double),
-                ("mass_new", ctypes.c_double), ("q_bathy", ctypes.c_double)]
+                ("mass_new", ctypes.c_double), ("q_bathy", ctypes.c_double), ("boundary_data_kept", ctypes.c_int32)]
 
 
 AMR_INDICATOR = {"vorticity": 0, "tracer_grad": 1}

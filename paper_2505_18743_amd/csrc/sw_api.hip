@@ -415,6 +415,7 @@ struct sw_ctx {
   double* d_ghost = nullptr;
   int64_t ng = 0;
   std::vector<int> gface;
+  std::vector<int> gcell, gside;   // cell (fine or equal side) and side of each of those faces
   bool ghost_set = false;
   int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
@@ -1091,8 +1092,11 @@ extern "C" {
 
 const char* sw_last_error(void) { return g_err.c_str(); }
 
-sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* meshes, const sw_params* params,
-                          void* stream) {
+// trusted: the meshes come from the library's own remesh plan (sorted,
+// in range, tiling, 2:1 balanced by construction), so the per-cell
+// duplicate, tiling and one-face-per-side checks are skipped
+static sw_status create_ctx(sw_ctx** out, int32_t n_members, const sw_mesh_desc* meshes, const sw_params* params,
+                            void* stream, bool trusted) {
   if (!out || !meshes || !params) return fail(SW_EINVAL, "NULL argument to sw_create_batch");
   *out = nullptr;
   if (n_members < 1) return fail(SW_EINVAL, "n_members must be >= 1");
@@ -1191,10 +1195,11 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
         return bail(SW_EINVAL, "cell outside the domain");
       maxL = std::max(maxL, L);
       area += (int64_t)1 << (sh - 2 * L);
-      if (leaf[m].get(L, md.i[k], md.j[k]) != -1) return bail(SW_EINVAL, "duplicate cell");
+      if (!trusted && leaf[m].get(L, md.i[k], md.j[k]) != -1) return bail(SW_EINVAL, "duplicate cell");
       leaf[m].set(L, md.i[k], md.j[k], k);
     }
-    if (area != ((int64_t)md.nx0 * md.ny0) << sh) return bail(SW_EINVAL, "cells do not tile the domain");
+    if (!trusted && area != ((int64_t)md.nx0 * md.ny0) << sh)
+      return bail(SW_EINVAL, "cells do not tile the domain");
     Ktot += md.n_cells;
   }
   if (Ktot > (int64_t)1 << 30) return bail(SW_EINVAL, "too many cells");
@@ -1214,20 +1219,30 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   for (int m = 0; m < M; ++m) ctx_of[m].assign(meshes[m].n_cells, -1);
   {
     int64_t off = 0;
+    c->cmem.reserve(K);
+    c->cloc.reserve(K);
+    c->lev.reserve(K);
+    c->ci.reserve(K);
+    c->cj.reserve(K);
+    c->cdx.reserve(K);
+    // each member's cells are sorted by level: one cursor per member
+    std::vector<int> cur(M, 0);
     for (auto& L : c->lv) {
       L.cell0 = (int)c->cmem.size();
       for (int m = 0; m < M; ++m) {
         const sw_mesh_desc& md = meshes[m];
-        for (int k = 0; k < md.n_cells; ++k) {
-          if (md.level[k] != L.L) continue;
+        const double dxl = md.dx0 / std::ldexp(1.0, L.L);
+        int k = cur[m];
+        for (; k < md.n_cells && md.level[k] == L.L; ++k) {
           ctx_of[m][k] = (int)c->cmem.size();
           c->cmem.push_back(m);
           c->cloc.push_back(k);
           c->lev.push_back(L.L);
           c->ci.push_back(md.i[k]);
           c->cj.push_back(md.j[k]);
-          c->cdx.push_back(md.dx0 / std::ldexp(1.0, L.L));
+          c->cdx.push_back(dxl);
         }
+        cur[m] = k;
       }
       L.ncell = (int)c->cmem.size() - L.cell0;
       L.off = (size_t)off;
@@ -1311,15 +1326,20 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
     fh.swap(sorted);
   }
   c->F = (int)fh.size();
-  std::vector<int> fA(c->F), fB(c->F), meta(c->F), used((size_t)K * 8, 0), fmem(c->F);
+  std::vector<int> fA(c->F), fB(c->F), meta(c->F), used(trusted ? 0 : (size_t)K * 8, 0), fmem(c->F);
   for (int f = 0; f < c->F; ++f) {
     const FaceH& h = fh[f];
     fA[f] = h.a;
     fB[f] = h.b;
     fmem[f] = c->cmem[h.a];
     meta[f] = h.sa | (h.sb << 2) | ((h.sub + 1) << 4) | (h.bnd << 6) | (h.bc << 8);
-    if (h.bnd && (h.bc == SW_BC_STATE || h.bc == SW_BC_DISCHARGE)) c->gface.push_back(f);
+    if (h.bnd && (h.bc == SW_BC_STATE || h.bc == SW_BC_DISCHARGE)) {
+      c->gface.push_back(f);
+      c->gcell.push_back(h.a);
+      c->gside.push_back(h.sa);
+    }
     // every cell side carries one face, or two sub-faces on a coarse side
+    if (trusted) continue;
     if (used[(size_t)h.a * 8 + h.sa * 2]++) return bail(SW_EINVAL, "two faces on one cell side");
     if (!h.bnd && used[(size_t)h.b * 8 + h.sb * 2 + (h.sub < 0 ? 0 : h.sub)]++)
       return bail(SW_EINVAL, "two faces on one cell side");
@@ -1433,6 +1453,7 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
   // host data goes to the device through one pinned staging buffer with
   // asynchronous copies on the context's stream, awaited at the end
   Uploads up;
+  up.blob.reserve(((size_t)40 * K + (size_t)28 * c->F + 4096) * 2);
 #define H2D(dst, src, n) up.add((void*)(dst), (const void*)(src), (size_t)(n) * sizeof(*(src)))
 #define ZERO(dst, bytes)                                                                       \
   do {                                                                                         \
@@ -1521,6 +1542,11 @@ sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* m
 #undef ZERO
   *out = c;
   return SW_OK;
+}
+
+sw_status sw_create_batch(sw_ctx** out, int32_t n_members, const sw_mesh_desc* meshes, const sw_params* params,
+                          void* stream) {
+  return create_ctx(out, n_members, meshes, params, stream, false);
 }
 
 sw_status sw_create(sw_ctx** out, const sw_mesh_desc* m, const sw_params* p, void* stream) {
@@ -2490,6 +2516,7 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
   if (P.n_refined == 0 && P.n_coarsened == 0) {
     S.mass_new = S.mass_old;
     S.q_bathy = 0.0;
+    S.boundary_data_kept = c->ghost_set ? 1 : 0;
     if (out) *out = S;
     return SW_OK;
   }
@@ -2510,7 +2537,7 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
   md.j = P.cj.data();
   for (int sd = 0; sd < 4; ++sd) md.bc[sd] = c->mbc[0][sd];
   sw_ctx* n = nullptr;
-  if ((st = sw_create_batch(&n, 1, &md, &c->p, c->s)) != SW_OK) return st;
+  if ((st = create_ctx(&n, 1, &md, &c->p, c->s, true)) != SW_OK) return st;
   auto drop = [&](sw_status e) {
     (void)hipStreamSynchronize(c->s);
     delete n;
@@ -2566,6 +2593,19 @@ sw_status sw_remesh(sw_ctx* c, const sw_amr_params* ap, sw_amr_stats* out) {
     return drop(fail(SW_EHIP, std::string("sw_remesh: ") + hipGetErrorString(e)));
   // the bathymetry of the new cells (with the transferred bed offsets)
   if ((st = sample_grid(n)) != SW_OK) return drop(st);
+  // given boundary data carry over when the faces that take them are the
+  // same cells' same sides, in the same order
+  bool keep = c->ghost_set && c->ng > 0 && n->ng == c->ng && n->gface.size() == c->gface.size();
+  for (size_t g = 0; keep && g < c->gface.size(); ++g) {
+    const int a = c->gcell[g], b = n->gcell[g];
+    keep = c->gside[g] == n->gside[g] && c->lev[a] == n->lev[b] && c->ci[a] == n->ci[b] && c->cj[a] == n->cj[b];
+  }
+  if (keep) {
+    if ((e = d2d(n->d_ghost, c->d_ghost, sizeof(double) * 4 * (size_t)c->ng)) != hipSuccess)
+      return drop(fail(SW_EHIP, std::string("sw_remesh: ") + hipGetErrorString(e)));
+    n->ghost_set = true;
+  }
+  S.boundary_data_kept = keep ? 1 : 0;
   double bathy_new = 0.0;
   if ((st = amr_mass(n, S.mass_new, bathy_new)) != SW_OK) return drop(st);
   S.q_bathy = bathy_new - bathy_old;

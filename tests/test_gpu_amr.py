@@ -266,6 +266,31 @@ def test_vortex_amr_matches_static(nmax):
     assert ad < 0.5 * sd
 
 
+def test_boundary_data_carry_over():
+    say("case: vortex AMR, the inflow side's data carry over a remesh that leaves its faces alone")
+    from paper_2505_18743_amd import Solver
+    v = Vortex()
+    out = []
+    for reset in (False, True):
+        o, s, grid = vortex_case(20, 2)
+        init = l2_project(o.m, 1, lambda x, y: exact_fn(v, 0.0)(x, y)[:3])
+        s.set_state(*init)
+        s.set_boundary_state(exact_fn(v, 0.0))
+        for _ in range(3):
+            s.step(1e-4)
+        st = s.remesh("vorticity", 1e-4, 5e-5, 2)
+        assert st["n_refined"] > 0 and st["boundary_data_kept"] == 1
+        if reset:
+            s.set_boundary_state(exact_fn(v, 0.0))
+        for _ in range(3):
+            s.step(1e-4)
+        s.sync()
+        out.append([cpu(x, s.n_cells) for x in s.get_state()[:3]])
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_amr_argument_checks():
     from paper_2505_18743_amd import Solver
     say("case: AMR argument checks")
