@@ -49,7 +49,7 @@ N_SIMD = 256 * 4
 CLOCK_HZ = 2.4e9
 VALU_CYCLES = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "element_stage_beach_dambreak_256.traffic.json")
-STAGE_SOURCES = ["sw_stage.inc", "sw_dev.h", "sw_internal.h", "sw_stage_r2.hip"]
+STAGE_SOURCES = ["sw_stage.inc", "sw_dev.h", "sw_internal.h", "sw_stage_dispatch.inc", "sw_stage_r2.hip"]
 
 
 def stage_source_sha():
