@@ -65,8 +65,10 @@ ambiguous or garbled (each one is also listed in the design notes):
     going from r to 0 is remapped conservatively: zeta-bar solves
     Hbar(zeta-bar) = Hbar(zeta^n), q-bar is the cell mean, c-bar = int(hc)/Hbar.
   * Tracer in a dry cell keeps its start-of-step value.  A cell counts as dry
-    when Hbar <= 1e-12 eps |K|: zero up to the round-off water that the dry
-    lift of eq:initial_guess and the scalar solve of Hbar = 0 can leave.
+    when Hbar <= 64 u |z_max| |K| (u = 2^-52, z_max the cell's largest depth
+    sample): zero up to the round-off water that the scalar solve of
+    Hbar = 0 leaves, where zeta + z_b cancels to a few ulps of |z_max| at the
+    deepest nodes.
   * Tracer numerical diffusion (eq:numdiff) is the volume term as printed,
     - int nu h grad c . grad psi_i with the plain depth, on the sample rule,
     with nu_K = C |K| r^-2 S; the characteristic strain rate S of the
@@ -879,11 +881,15 @@ class Oracle:
             active = active & ~conv & (Awet > 0)
         return z, its, h, H, Hbar, fallback_used
 
+    def _dry_floor(self, lv):
+        """Round-off water of a dry cell: 64 u |z_max| |K| (u = 2^-52)."""
+        return 64.0 * 2.0 ** -52 * self.zb_eff(lv).max(1).values.abs() * lv.dx ** 2
+
     def _tracer_solve(self, lv, h, CT, c_keep, full):
         """hc-mass system (eq:algebraic_concentration, eq:mass_matrix_concentration)."""
         W, Bv = lv.W, lv.Bv
         Hbar = (W * h).sum(1)
-        wet = Hbar > 1e-12 * self.p.eps * lv.dx ** 2   # dry up to round-off water
+        wet = Hbar > self._dry_floor(lv)   # dry up to round-off water
         Hm = torch.einsum("kq,qi,qj->kij", W * h, Bv, Bv)
         x, ok = self._chol_solve(Hm, CT)
         # constant-mode fallback: c = c_keep + s with sum_i (Hm (c_keep + s))_i = sum CT
@@ -926,7 +932,7 @@ class Oracle:
                 znew, _, _, _, _, _ = self._newton(lv, rpos, Tn, zguess, full0)
                 hc = (lv.W * h[remap] * (c[ridx] @ lv.Bv.T)).sum(1)
                 cmean = c[ridx] @ self.mean_w
-                wet = Hbar > 1e-12 * p.eps * lv.dx ** 2
+                wet = Hbar > self._dry_floor(lv)[remap]
                 cbar = torch.where(wet, hc / torch.where(wet, Hbar, torch.ones_like(Hbar)), cmean)
                 zeta[ridx] = znew[:, :1].expand(-1, self.np_)
                 qx[ridx] = (qx[ridx] @ self.mean_w)[:, None].expand(-1, self.np_)

@@ -219,4 +219,12 @@ __device__ __forceinline__ double gamma_plain(double h, double qx, double qy, do
   return gn2 * qn * (ih * ih) * c;
 }
 
+// Round-off water of a dry cell: 64 u |z_max| |K| (u = 2^-52), the mass the
+// scalar solve of Hbar = 0 can leave where zeta + z_b cancels to a few ulps
+// of the largest depth sample.  A cell with no more water than this counts
+// as dry for the tracer (its concentration is kept).
+__device__ __forceinline__ double dry_floor(double zmax, double area) {
+  return 0x1p-46 * fabs(zmax) * area;
+}
+
 }  // namespace swk
