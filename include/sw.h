@@ -220,6 +220,11 @@ sw_status sw_get_state(const sw_ctx *c, double *eta, double *qx, double *qy, dou
  * (eta(x_q) - b(x_q) > 0), zeta_j = min_q b(x_q) elsewhere; q = 0. */
 sw_status sw_init_lake_at_rest(sw_ctx *c, const double *eta_dev);
 sw_status sw_set_time(sw_ctx *c, double t);
+/* The elevation boundary's data (SW_BC_ELEV, Sec. 4.5's M2 tide) of every
+ * member, replacing sw_params.tide_*: zeta = amplitude sin(2 pi t / period +
+ * phase) at the face nodes and c_inflow taken by the tracer on inflow.
+ * period must be finite and non-zero (SW_EINVAL otherwise). */
+sw_status sw_set_tide(sw_ctx *c, double amplitude, double period, double phase, double c_inflow);
 
 /* Weak residuals of the degree-r test functions for the given state (device
  * inputs/outputs, [n_dofs] each; tracer/R may be NULL): F (eq:mass_rhs),
@@ -465,6 +470,8 @@ sw_status sw_ens_member(const sw_ens *e, int32_t m, int32_t *batch, int32_t *ind
  * taken eagerly when a batch has just been (re)initialised.  Results equal the
  * eager path's bit for bit.  Work is enqueued on `stream`. */
 sw_status sw_ens_run(sw_ens *e, int32_t n_steps, double dt, int32_t use_graph);
+/* One step of every member with its CFL time step: sw_ens_run(e, 1, 0, use_graph). */
+sw_status sw_ens_step(sw_ens *e, int32_t use_graph);
 /* Wait for all work of the ensemble; SW_EDEVICE as sw_sync. */
 sw_status sw_ens_sync(sw_ens *e);
 /* Launch-shape autotuner of every batch (sw_autotune with `steps` timed

@@ -27,7 +27,8 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_member_diagnostics", "sw_profile", "sw_kernel_time", "sw_kernel_time_reset", "sw_sync",
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
            "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
-           "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells", "sw_amr_plan"]
+           "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells", "sw_amr_plan", "sw_set_tide",
+           "sw_ens_step"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -131,6 +132,8 @@ def load():
     L.sw_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.sw_init_lake_at_rest.argtypes = [vp, vp]
     L.sw_set_time.argtypes = [vp, ctypes.c_double]
+    L.sw_set_tide.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.sw_ens_step.argtypes = [vp, ctypes.c_int32]
     L.sw_apply_operator.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
     L.sw_apply_operator_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
     L.sw_step_begin.argtypes = [vp, ctypes.c_double]
@@ -423,6 +426,11 @@ class Solver:
     def set_time(self, t):
         _check(load().sw_set_time(self.h, float(t)), "sw_set_time")
 
+    def set_tide(self, amplitude, period, phase=0.0, c_inflow=0.0):
+        """sw_set_tide: the elevation boundary's tide of every member."""
+        _check(load().sw_set_tide(self.h, float(amplitude), float(period), float(phase), float(c_inflow)),
+               "sw_set_tide")
+
     # ---- operator and stepping ----
     def apply_operator(self, eta, qx, qy, c=None, t=0.0):
         ins = [self._dev(a, self.n_dofs) for a in (eta, qx, qy)]
@@ -702,6 +710,10 @@ class Ensemble:
 
     def run(self, n, dt=0.0, graph=True):
         _check(load().sw_ens_run(self.h, int(n), float(dt), int(bool(graph))), "sw_ens_run")
+
+    def step(self, graph=True):
+        """sw_ens_step: one step of every member with its CFL time step."""
+        _check(load().sw_ens_step(self.h, int(bool(graph))), "sw_ens_step")
 
     def autotune(self, steps=8, cache=None):
         """Launch-shape autotuner of every batch; returns the chosen shapes."""

@@ -1774,6 +1774,29 @@ sw_status sw_set_time(sw_ctx* c, double t) {
   return SW_OK;
 }
 
+sw_status sw_set_tide(sw_ctx* c, double amplitude, double period, double phase, double c_inflow) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (!(std::fabs(amplitude) < 1e300) || !(std::fabs(period) < 1e300) || period == 0.0 ||
+      !(std::fabs(phase) < 1e300) || !(std::fabs(c_inflow) < 1e300))
+    return fail(SW_EINVAL, "tide data must be finite with a non-zero period");
+  if (c->stage_done != 0) return fail(SW_EINVAL, "sw_set_tide cannot run inside an open step");
+  std::vector<double> td(4 * (size_t)c->M);
+  for (int m = 0; m < c->M; ++m) {
+    td[4 * m + 0] = amplitude;
+    td[4 * m + 1] = period;
+    td[4 * m + 2] = phase;
+    td[4 * m + 3] = c_inflow;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_mtide, td.data(), td.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));   // the host vector goes out of scope
+  c->p.tide_amp = amplitude;
+  c->p.tide_period = period;
+  c->p.tide_phase = phase;
+  c->p.tide_c_in = c_inflow;
+  c->start_ready = false;
+  return SW_OK;
+}
+
 namespace {
 // The operator evaluation's own device scratch: the residual slot that the
 // volume and face kernels accumulate into (res, slot `slot`), the members'

@@ -244,6 +244,8 @@ sw_status sw_ens_run(sw_ens* e, int32_t n_steps, double dt, int32_t use_graph) {
   return SW_OK;
 }
 
+sw_status sw_ens_step(sw_ens* e, int32_t use_graph) { return sw_ens_run(e, 1, 0.0, use_graph); }
+
 sw_status sw_ens_autotune(sw_ens* e, int32_t steps, const char* cache_path) {
   if (!e) return efail(SW_EINVAL, "NULL ensemble");
   // cache: one line per batch class, "<key> <wavefronts per workgroup> <lanes per face>"

@@ -246,3 +246,22 @@ def test_ensemble_autotune_and_cache(tmp_path):
         one.close()
     ens.close()
     ens2.close()
+
+
+def test_ensemble_step_is_one_run_step():
+    say("case: sw_ens_step equals sw_ens_run with one step, 4 small members")
+    mem = small_members(4, 3, 6)
+    out = []
+    for use_step in (False, True):
+        ens, _ = setup_ensemble(mem)
+        for _ in range(3):
+            if use_step:
+                ens.step(graph=True)
+            else:
+                ens.run(1, graph=True)
+        ens.sync()
+        out.append([ens.get_state(m) for m in range(len(mem))])
+        ens.close()
+    for a, b in zip(*out):
+        for f in range(3):
+            assert same(a[f], b[f])

@@ -698,3 +698,30 @@ def test_steps_tidal_quadtree_window_c3_rule(where):
     assert dg["t"] == pytest.approx(o.t, rel=1e-12)
     assert dg["n_r0_cells"] == n_r0_next(o) and dg["max_newton_it"] == d["newton_it"]
     s.close()
+
+
+def test_set_tide_equals_the_created_tide():
+    """sw_set_tide on a context made without a tide gives the steps of a
+    context made with it, bit for bit (hanging mesh, elevation side, tracer)."""
+    say("case: sw_set_tide vs the tide of sw_params, hanging mesh, 10 steps")
+    o, b = hanging_case(2, (16, 8))
+    s1 = gpu_from_oracle(o, b)
+    p0 = oracle_params(o)
+    p0["tide"] = (0.0, 1.0, 0.0, 0.0)
+    from paper_2505_18743_amd import Solver
+    s2 = Solver(mesh_dict(o.m), p0, device="cuda:0")
+    s2.set_bathymetry(b)
+    s2.set_manning(o.nman.numpy())
+    s2.set_tide(*o.p.tide)
+    with pytest.raises(RuntimeError, match="period"):
+        s2.set_tide(0.3, 0.0)
+    st = o.get_state()
+    for s in (s1, s2):
+        s.set_state(*st)
+        for _ in range(10):
+            s.step()
+        s.sync()
+    for f in range(4):
+        assert torch.equal(s1.get_state()[f], s2.get_state()[f]), f
+    s1.close()
+    s2.close()
