@@ -393,6 +393,17 @@ sw_status sw_amr_plan(const sw_mesh_desc *mesh, const double *eta_host, const sw
  * kernel sums in another order).  Requires params.tracer; the buffers are
  * read only. */
 sw_status sw_tracer_step(sw_ctx *c, const double *stages_dev, const double *end_dev, double dt);
+/* Several tracers (eq:shw with M > 1 passive tracers, each with its own
+ * diffusion and decay): one step of the flow context with the fixed dt > 0,
+ * recorded into buffers the flow context keeps (allocated on first use,
+ * (s + 1) x 3 x n_dofs doubles), then sw_tracer_step of each of the n
+ * tracer contexts over that record.  The tracer contexts must share the
+ * flow's mesh, degree and scheme (SW_EINVAL otherwise) and start each call
+ * with the flow's state, which sw_tracer_step keeps in step with the flow;
+ * the flow context may carry the first tracer itself.  Contexts on other
+ * streams are ordered with events; the next call's record waits for this
+ * call's replays. */
+sw_status sw_step_tracers(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, double dt);
 
 /* Diagnostics of the last step (host output).  Synchronises.  In a batched
  * context dt and t are member 0's; masses and counts are summed, extrema

@@ -28,7 +28,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
            "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
            "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells", "sw_amr_plan", "sw_set_tide",
-           "sw_ens_step"]
+           "sw_ens_step", "sw_step_tracers"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -132,6 +132,7 @@ def load():
     L.sw_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.sw_init_lake_at_rest.argtypes = [vp, vp]
     L.sw_set_time.argtypes = [vp, ctypes.c_double]
+    L.sw_step_tracers.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_double]
     L.sw_set_tide.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.sw_ens_step.argtypes = [vp, ctypes.c_int32]
     L.sw_apply_operator.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
@@ -476,6 +477,12 @@ class Solver:
 
     def sync(self):
         _check(load().sw_sync(self.h), "sw_sync")
+
+    def step_tracers(self, tracers, dt):
+        """sw_step_tracers: one fixed-dt step of this (flow) context and of the
+        given tracer Solvers over its recorded flow."""
+        arr = (ctypes.c_void_p * max(len(tracers), 1))(*[t.h for t in tracers])
+        _check(load().sw_step_tracers(self.h, len(tracers), arr, float(dt)), "sw_step_tracers")
 
     # ---- dynamic h-adaptivity ----
     def set_bed_grid(self, grid):

@@ -420,6 +420,8 @@ struct sw_ctx {
   int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
   const double* rp[3] = {nullptr, nullptr, nullptr};   // tracer replay: recorded flow of the current stage
+  double* d_trec = nullptr;   // sw_step_tracers: the flow record of one step ([ns][3][KN] stages, [3][KN] end)
+  hipEvent_t ev_rec = nullptr;  // sw_step_tracers: the record is complete / the tracers are done with it
   double* rec[3] = {nullptr, nullptr, nullptr};        // record of the final combination's flow
   bool fixed_dt = false;
   bool bathy_set = false;
@@ -449,6 +451,10 @@ struct sw_ctx {
   sw_ctx(const sw_ctx&) = delete;
   sw_ctx& operator=(const sw_ctx&) = default;
   void release() {
+    if (ev_rec) {
+      (void)hipEventDestroy(ev_rec);
+      ev_rec = nullptr;
+    }
     for (auto& e : ev) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -466,6 +472,7 @@ struct sw_ctx {
     *this = n;
     n.allocs.clear();
     n.ev.clear();
+    n.ev_rec = nullptr;
   }
   ~sw_ctx() { release(); }
   // bracket a group of launches of one kernel class with events when profiling
@@ -2028,6 +2035,40 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
   }
   point(nullptr);
   return st;
+}
+
+sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
+  if (!flow) return fail(SW_EINVAL, "NULL flow context");
+  if (n < 0 || (n > 0 && !tracers)) return fail(SW_EINVAL, "bad tracer context list");
+  if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_step_tracers needs a fixed dt > 0");
+  for (int i = 0; i < n; ++i) {
+    const sw_ctx* t = tracers[i];
+    if (!t || t == flow) return fail(SW_EINVAL, "tracer context " + std::to_string(i) + " is NULL or the flow's");
+    if (!t->p.tracer) return fail(SW_EINVAL, "tracer context " + std::to_string(i) + " has no tracer");
+    if (t->K != flow->K || t->NP != flow->NP || t->ns != flow->ns || t->M != flow->M || t->lev != flow->lev ||
+        t->ci != flow->ci || t->cj != flow->cj || t->cdx != flow->cdx || t->dev != flow->dev)
+      return fail(SW_EINVAL, "tracer context " + std::to_string(i) + ": mesh, degree or scheme differ from the flow's");
+  }
+  const size_t KN = (size_t)flow->K * flow->NP;
+  sw_status st = SW_OK;
+  if (!flow->d_trec && (st = flow->alloc(&flow->d_trec, (size_t)(flow->ns + 1) * 3 * KN)) != SW_OK) return st;
+  if (!flow->ev_rec) HIPCHK(hipEventCreateWithFlags(&flow->ev_rec, hipEventDisableTiming));
+  double* stages = flow->d_trec;
+  double* end = flow->d_trec + (size_t)flow->ns * 3 * KN;
+  if ((st = sw_step_record(flow, dt, stages, end)) != SW_OK) return st;
+  HIPCHK(hipEventRecord(flow->ev_rec, flow->s));
+  for (int i = 0; i < n; ++i) {
+    sw_ctx* t = tracers[i];
+    if (t->s != flow->s) HIPCHK(hipStreamWaitEvent(t->s, flow->ev_rec, 0));
+    if ((st = sw_tracer_step(t, stages, end, dt)) != SW_OK) return st;
+    // the next call's record waits for this replay
+    if (t->s != flow->s) {
+      if (!t->ev_rec) HIPCHK(hipEventCreateWithFlags(&t->ev_rec, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(t->ev_rec, t->s));
+      HIPCHK(hipStreamWaitEvent(flow->s, t->ev_rec, 0));
+    }
+  }
+  return SW_OK;
 }
 
 }  // extern "C"

@@ -105,3 +105,51 @@ def test_several_tracers_over_one_recorded_flow():
         assert e < TOL_STEP
         rep.close()
     rec.close()
+
+
+def test_step_tracers_one_call():
+    say("case: sw_step_tracers, a flow context with its own tracer and two more tracers, 12 steps")
+    o, b = hanging_case(2, (16, 8))
+    st0 = o.get_state()
+    flow = gpu_from_oracle(o, b)
+    dt = fixed_dt(flow, st0)
+    dof = o.dof_coords()
+    srcs = [dict(tracer_diff=0.33, tracer_strain=0.004, tracer_decay=0.0),
+            dict(tracer_diff=0.0, tracer_strain=0.0, tracer_decay=5e-3)]
+    inits = [np.where(dof[..., 0] < 1300.0, 1.0, 0.25), 0.5 + 0.3 * np.cos(dof[..., 0] / 300.0)]
+    ctxs = []
+    for src in srcs:
+        oi, _ = hanging_case(2, (16, 8))
+        ctxs.append(gpu_from_oracle(with_sources(oi, **src), b))
+    flow.set_state(*st0)
+    flow.set_time(0.0)
+    for t, c in zip(ctxs, inits):
+        t.set_state(st0[0], st0[1], st0[2], c)
+        t.set_time(0.0)
+    n = 12
+    for _ in range(n):
+        flow.step_tracers(ctxs, dt)
+    flow.sync()
+    got = [t.get_state() for t in ctxs]
+    # the flow itself equals its plain coupled run; each tracer its own coupled run
+    ref = gpu_from_oracle(o, b)
+    ref.set_state(*st0)
+    for _ in range(n):
+        ref.step(dt)
+    ref.sync()
+    for f in range(4):
+        assert torch.equal(flow.get_state()[f], ref.get_state()[f]), f
+    for t, c, g in zip(ctxs, inits, got):
+        t.set_state(st0[0], st0[1], st0[2], c)
+        t.set_time(0.0)
+        for _ in range(n):
+            t.step(dt)
+        t.sync()
+        own = t.get_state()
+        for f in range(4):
+            assert torch.equal(g[f], own[f]), f
+        t.close()
+    with pytest.raises(RuntimeError, match="flow"):
+        flow.step_tracers([flow], dt)
+    flow.close()
+    ref.close()
