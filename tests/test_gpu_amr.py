@@ -139,10 +139,10 @@ def check_remesh(o, s, grid, kind, name, tr, tc, nmax, label):
     return n, st
 
 
-@pytest.mark.parametrize("quadrature", ["subgrid", "paper"])
-def test_remesh_and_steps_parity(quadrature):
-    say(f"case: remesh between steps, two to three levels, wet/dry, raster bed, {quadrature} quadrature")
-    o, grid = coastal_amr(quadrature=quadrature)
+@pytest.mark.parametrize("quadrature,rk", [("subgrid", "ssp3"), ("paper", "ssp3"), ("subgrid", "imex")])
+def test_remesh_and_steps_parity(quadrature, rk):
+    say(f"case: remesh between steps, two to three levels, wet/dry, raster bed, {quadrature} quadrature, {rk}")
+    o, grid = coastal_amr(quadrature=quadrature, rk=rk)
     s = gpu_amr(o, grid)
     for _ in range(5):
         o.step()
