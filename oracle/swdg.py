@@ -76,6 +76,11 @@ ambiguous or garbled (each one is also listed in the design notes):
     the run.  A first-order decay, the reaction phi(c) = -kappa c of eq:shw,
     enters R as - kappa int h c psi_i (explicit, as eq:imex_shw takes the
     reactions).
+  * Reactions that couple tracers (step_coupled) are the linear
+    phi_k = sum_j B_kj c_j: R_k of every stage gets sum_j B_kj int h c_j psi_i
+    of that stage's state on the volume rule, for every tracer before any
+    takes the next stage.  The paper leaves the reaction terms' full
+    discretisation open and names no rates.
 """
 from __future__ import annotations
 
@@ -956,6 +961,19 @@ class Oracle:
     def step(self, dt=None):
         """One explicit RK step in Butcher form (Sec. 3.1, eq:algebraic_elevation,
         eq:algebraic_discharge, eq:algebraic_concentration)."""
+        gen = self.stepper(dt)
+        while True:
+            try:
+                next(gen)
+            except StopIteration as done:
+                return done.value
+
+    def stepper(self, dt=None):
+        """The step of ``step`` taken stage by stage: after the residual of each
+        stage state u^(l) it yields (l, u^(l), [F, Gx, Gy, R]) and resumes once
+        the caller is done with them; a caller may add to R (the reaction
+        source of eq:shw, explicit in every stage as in eq:imex_shw) before it
+        resumes.  Returns the step's diagnostics."""
         p = self.p
         A, b, cc = tableau(p.rk)
         imp = implicit_tableau(p.rk)     # IMEX: friction with the DIRK companion
@@ -1051,7 +1069,8 @@ class Oracle:
                     dt = p.cfl * float(dtb)
                     if l == 0 and cc[0] != 0.0:
                         raise ValueError("first stage must have c = 0")
-                res.append((F, Gx, Gy, R))
+                res.append([F, Gx, Gy, R])
+                yield l, cur, res[l]
         self.state = cur
         self.t = t0 + dt
         mass = 0.0
@@ -1125,6 +1144,22 @@ class Oracle:
             Gam[idx] = torch.einsum("kq,qi,qj->kij", W * gam_h, Bv, Bv)
         return Lx, Ly, Gam
 
+    def hc_moments(self, state):
+        """int h c psi_i over each cell on the volume rule (the rule of the
+        residual's volume terms), with h the plain depth of the state's zeta:
+        the source int h phi psi_i of eq:shw for phi = c."""
+        zeta, c = state[0], state[3]
+        S = torch.zeros_like(zeta)
+        for lv in self.levels:
+            idx = lv.idx
+            if len(idx) == 0:
+                continue
+            vr = lv if lv.vol is None else _Vol(lv.vol)
+            zbv = self.zb_eff(lv) if lv.vol is None else self.zb_vol_eff(lv)
+            h = _pos(zeta[idx] @ vr.Bv.T + zbv)
+            S[idx] = (vr.W * h * (c[idx] @ vr.Bv.T)) @ vr.Bv
+        return S
+
     def apply_operator(self, state=None, t=None):
         st = self.state if state is None else [torch.as_tensor(np.asarray(s, dtype=np.float64)).reshape(self.m.K, self.np_) for s in state]
         F, Gx, Gy, R, dtb = self.residual(st, self.t if t is None else t)
@@ -1160,3 +1195,47 @@ class Oracle:
             _, _, H = self._depth_terms(lv, torch.arange(len(lv.idx)), self.state[0][lv.idx])
             Hn[lv.idx] = H
         return Hn.numpy()
+
+
+def step_coupled(oracles, B, dt):
+    """One step of M tracers c_1..c_M carried by one flow, with the linear
+    reactions phi_k(c_1, ..., c_M) = sum_j B_kj c_j of eq:shw.
+
+    Each tracer is an Oracle of its own whose flow is the same (same mesh,
+    parameters, bathymetry and flow state), so their flows are identical.  The
+    steps run stage by stage together: the reaction enters every stage
+    explicitly, as eq:imex_shw takes it,
+
+        h^(l) c_k^(l) = h^n c_k^n - dt sum_m a_lm (div(q c_k))^(m)
+                        + dt sum_m a_lm h^(m) phi_k(c^(m)),
+
+    so after the residuals of stage m each tracer's R gets
+    sum_j B_kj int h^(m) c_j^(m) psi_i before any tracer takes stage m + 1.
+    dt must be given.  Returns each tracer's step diagnostics.
+    """
+    B = np.asarray(B, dtype=np.float64)
+    M = len(oracles)
+    if B.shape != (M, M):
+        raise ValueError("B must be M x M for M tracers")
+    if dt is None or not dt > 0.0:
+        raise ValueError("the coupled step needs a fixed dt > 0")
+    gens = [o.stepper(dt) for o in oracles]
+    diags = [None] * M
+    while True:
+        outs = []
+        for k, g in enumerate(gens):
+            try:
+                outs.append(next(g))
+            except StopIteration as done:
+                diags[k] = done.value
+        if not outs:
+            return diags
+        if len(outs) != M:
+            raise RuntimeError("the tracers' steps have different numbers of stages")
+        Sm = [o.hc_moments(cur) for o, (_, cur, _) in zip(oracles, outs)]
+        for k, (_, _, res) in enumerate(outs):
+            src = torch.zeros_like(res[3])
+            for j in range(M):
+                if B[k, j] != 0.0:
+                    src = src + B[k, j] * Sm[j]
+            res[3] = res[3] + src
