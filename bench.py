@@ -585,6 +585,116 @@ def vortex_bench(device, N=320):
 
 
 # Table 7, with AMR at n_max = 5: wall time (s, 8 CPU processes) and DoFs
+def react_work(S, r, M):
+    """Algorithmic bytes and flops of the reaction kernel for one cell and
+    M tracers on an S x S rule.  Bytes: the depth samples and zeta once, each
+    tracer's concentration, the read and write of each tracer's residual R,
+    the cell size.  Flops (sum factorisation, one lane a node row): the
+    y-interpolated row coefficients of zeta and of each c_j, then per node the
+    depth (an (r+1)-term interpolation, the weights and the mask) and per
+    tracer c_j, w h c_j and its (r+1) x-projections, the y-projections of the
+    (r+1)^2 row partials, and the M x M combination."""
+    N1 = r + 1
+    NP = N1 * N1
+    nb = 8 * (S * S + NP + M * NP + 2 * M * NP + 1)
+    fl = (2 * N1 * N1 * S + S * S * (2 * N1 + 4)
+          + M * (2 * N1 * N1 * S + S * S * (4 * N1 + 1) + 2 * NP * S) + 2 * M * M * NP)
+    return nb, fl
+
+
+def tracers_bench(device, steps=20, M=3):
+    """M tracers carried by the 256x256 beach flow (r=2, 16x16 samples, SSP3,
+    fixed dt = the flow's first CFL step): the flow alone (sw_step), the flow
+    recorded and the tracers replayed over it (sw_step_tracers), and the same
+    with linear reactions between the tracers (sw_step_tracers_react, a
+    conversion chain with feedback).  Tracer DoF-updates/s of both and the
+    reaction kernel's launch time against its algorithmic bytes and flops."""
+    import numpy as np
+    import torch
+    from paper_2505_18743_amd import Solver
+    from workloads import workload
+    wl = workload("beach_dambreak_256")
+    flow, reset, bed = setup(wl, device)
+    p = dict(wl["params"])
+    p["tracer"] = True
+    ctxs = []
+    for _ in range(M):
+        t = Solver(wl["mesh"], p, device=device)
+        t.set_bathymetry(bed)
+        t.set_manning(wl["manning"])
+        ctxs.append(t)
+    dof = flow.dof_coords()
+    x = (dof[:, 0] - dof[:, 0].min()) / np.ptp(dof[:, 0])
+    y = (dof[:, 1] - dof[:, 1].min()) / np.ptp(dof[:, 1])
+    cs = [np.where(x < 0.5, 1.0, 0.2), 0.5 + 0.3 * np.cos(6.0 * y), 0.1 + 0.05 * np.sin(8.0 * (x + y))]
+    cs = (cs * M)[:M]
+
+    def restart():
+        reset()
+        st = flow.get_state()
+        for t, c in zip(ctxs, cs):
+            t.set_state(st[0], st[1], st[2], c)
+            t.set_time(0.0)
+    flow.step()
+    flow.sync()
+    dt = float(flow.diagnostics()["dt"])
+    base = np.array([[-1.0, 0.0, 0.3], [0.8, -0.5, 0.0], [0.2, 0.5, -0.3]])
+    B = np.zeros((M, M))
+    B[:min(M, 3), :min(M, 3)] = base[:min(M, 3), :min(M, 3)]
+    B = B * (0.01 / dt)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        restart()
+        fn()
+        fn()
+        restart()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+    ms_flow = timed(lambda: flow.step(dt))
+    ms_plain = timed(lambda: flow.step_tracers(ctxs, dt))
+    ms_react = timed(lambda: flow.step_tracers_react(ctxs, B, dt))
+    # the reaction kernel's launches, timed with events on the library's stream
+    restart()
+    torch.cuda.synchronize()
+    ctxs[0].profile(True, kinds=["reactions"])
+    ctxs[0].kernel_time_reset()
+    for _ in range(steps):
+        flow.step_tracers_react(ctxs, B, dt)
+    torch.cuda.synchronize()
+    k_ms, k_n = ctxs[0].kernel_times()["reactions"]
+    ctxs[0].profile(False)
+    flow.sync()
+    r = int(wl["params"]["r"])
+    S = int(wl["params"]["S"][0])
+    stages = {"fe": 1, "ssp3": 3, "rk32": 3, "rk44": 4}[wl["params"]["rk"]]
+    K = flow.n_cells
+    tdofs = M * (r + 1) ** 2 * K * stages
+    nb, fl = react_work(S, r, M)
+    launch_s = k_ms * 1e-3 / max(k_n, 1)
+    gbs = nb * K / launch_s / 1e9
+    tfl = fl * K / launch_s / 1e12
+    for t in ctxs:
+        t.close()
+    flow.close()
+    return dict(workload=f"beach_dambreak_256 flow + {M} tracers", cells=K, tracers=M, steps=steps, dt=dt,
+                ms_per_step=dict(flow=round(ms_flow, 4), tracers=round(ms_plain, 4), reacting=round(ms_react, 4)),
+                reaction_ms_per_step=round(ms_react - ms_plain, 4),
+                tracer_value=dict(tracers=tdofs / ((ms_plain - ms_flow) * 1e-3),
+                                  reacting=tdofs / ((ms_react - ms_flow) * 1e-3), unit="tracer DoF-updates/s"),
+                react_kernel=dict(kernel=f"k_react<r={r},P={lanes_for(S)}> ({S}x{S} nodes, one lane a node row)",
+                                  launches=k_n, us_per_launch=round(launch_s * 1e6, 2),
+                                  algo_bytes_per_launch=nb * K, algo_flops_per_launch=fl * K,
+                                  gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                                  tflops=round(tfl, 3), fp64_frac=round(tfl / FP64_PEAK_TFLOPS, 4)))
+
+
 PAPER_VORTEX_AMR = [("rk32", 1, 74.1, 267_828), ("ssp3", 2, 286.7, 590_949), ("rk44", 3, 531.1, 1_028_256)]
 
 
@@ -727,7 +837,8 @@ def main():
     ap.add_argument("--imex-steps", type=int, default=100, help="beach steps of the IMEX leg (0: skip)")
     ap.add_argument("--no-vortex", action="store_true", help="skip the travelling-vortex wall-time leg")
     ap.add_argument("--no-vortex-amr", action="store_true", help="skip the adaptive travelling-vortex leg")
-    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex", "vortex", "vortex_amr"],
+    ap.add_argument("--no-tracers", action="store_true", help="skip the reacting-tracers leg")
+    ap.add_argument("--only", choices=["ensemble", "adjoint", "quadtree", "imex", "vortex", "vortex_amr", "tracers"],
                     default=None,
                     help="run only that leg (for profiling it on its own); prints its JSON object")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -764,6 +875,9 @@ def main():
         return
     if args.only == "vortex_amr":
         print(json.dumps(vortex_amr_bench(dev)), flush=True)
+        return
+    if args.only == "tracers":
+        print(json.dumps(tracers_bench(dev)), flush=True)
         return
     wl = workload(args.workload)
     s, reset, _ = setup(wl, dev)
@@ -871,6 +985,9 @@ def main():
         line["vortex"] = vortex_bench(dev)
     if not args.no_vortex_amr:
         line["vortex_amr"] = vortex_amr_bench(dev)
+    if not args.no_tracers:
+        progress("reacting tracers")
+        line["tracers"] = tracers_bench(dev)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host)")
         line["cpu_baseline"] = cpu_baseline(args.workload)

@@ -404,6 +404,22 @@ sw_status sw_tracer_step(sw_ctx *c, const double *stages_dev, const double *end_
  * streams are ordered with events; the next call's record waits for this
  * call's replays. */
 sw_status sw_step_tracers(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, double dt);
+/* Tracers that react with each other: sw_step_tracers with the reactions
+ * h phi_k(c_1, ..., c_n) of eq:shw, phi_k = sum_j B_kj c_j, between the n
+ * tracer contexts (1 <= n <= 8), taken explicitly in every stage as
+ * eq:imex_shw takes them.  react_host is B, n x n doubles row-major
+ * (B_kj at react_host[k n + j], 1/s, finite), read during the call; NULL
+ * runs sw_step_tracers.  The tracer contexts step stage by stage together:
+ * after each stage's residuals, context k's tracer residual gets
+ * sum_j B_kj int h c_j psi_i of that stage's states, integrated on the
+ * volume rule with the plain depth, before any context takes the next
+ * stage.  The tracer contexts carry the flow's bathymetry and state, so that
+ * depth is taken from the first of them.  Each context's own decay (params.tracer_decay) and diffusion still
+ * apply.  Every launch of the call runs on the flow context's stream, after
+ * the tracer contexts' earlier work; their streams wait for its end.  A
+ * context listed twice, or the flow context itself, is SW_EINVAL. */
+sw_status sw_step_tracers_react(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, const double *react_host,
+                                double dt);
 
 /* Diagnostics of the last step (host output).  Synchronises.  In a batched
  * context dt and t are member 0's; masses and counts are summed, extrema
@@ -422,6 +438,8 @@ sw_status sw_member_diagnostics(const sw_ctx *c, int32_t member, sw_diag *out_ho
  *           the cells the fast element kernel keeps)
  *   kind 6: fast tracer kernel at step begin and of the final combination (+ C~ of
  *           the next step).
+ *   kind 7: reaction kernel of sw_step_tracers_react (counted on the first
+ *           tracer context).
  * sw_kernel_time_reset clears the totals.  on = 0: off; 1: every class;
  * on = 1 | (mask << 1) with mask != 0: only the classes whose bit is set in
  * mask (fewer events, less perturbation).  The events are timing-only (no

@@ -28,7 +28,7 @@ EXPORTS = ["sw_create", "sw_destroy", "sw_last_error", "sw_create_batch", "sw_ce
            "sw_ens_create", "sw_ens_destroy", "sw_ens_batches", "sw_ens_batch", "sw_ens_member", "sw_ens_run",
            "sw_ens_sync", "sw_vjp_operator", "sw_step_record", "sw_vjp_step", "sw_tracer_step", "sw_locate_points", "sw_boundary_nodes", "sw_set_boundary_state", "sw_set_workgroup", "sw_get_workgroup", "sw_autotune",
            "sw_ens_autotune", "sw_set_bed_grid", "sw_amr_indicator", "sw_remesh", "sw_cells", "sw_amr_plan", "sw_set_tide",
-           "sw_ens_step", "sw_step_tracers"]
+           "sw_ens_step", "sw_step_tracers", "sw_step_tracers_react"]
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.c_void_p
@@ -133,6 +133,7 @@ def load():
     L.sw_init_lake_at_rest.argtypes = [vp, vp]
     L.sw_set_time.argtypes = [vp, ctypes.c_double]
     L.sw_step_tracers.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_double]
+    L.sw_step_tracers_react.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double]
     L.sw_set_tide.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.sw_ens_step.argtypes = [vp, ctypes.c_int32]
     L.sw_apply_operator.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
@@ -484,6 +485,16 @@ class Solver:
         arr = (ctypes.c_void_p * max(len(tracers), 1))(*[t.h for t in tracers])
         _check(load().sw_step_tracers(self.h, len(tracers), arr, float(dt)), "sw_step_tracers")
 
+    def step_tracers_react(self, tracers, react, dt):
+        """sw_step_tracers_react: step_tracers with the linear reactions
+        phi_k = sum_j react[k][j] c_j between the given tracer Solvers (react:
+        an n x n matrix, 1/s)."""
+        n = len(tracers)
+        B = np.ascontiguousarray(np.asarray(react, dtype=np.float64).reshape(n, n))
+        arr = (ctypes.c_void_p * max(n, 1))(*[t.h for t in tracers])
+        _check(load().sw_step_tracers_react(self.h, n, arr, B.ctypes.data_as(ctypes.c_void_p), float(dt)),
+               "sw_step_tracers_react")
+
     # ---- dynamic h-adaptivity ----
     def set_bed_grid(self, grid):
         """Bathymetry raster: grid = dict(x0, y0, dx, dy, b [ny, nx]) of bed
@@ -601,7 +612,7 @@ class Solver:
         _check(load().sw_profile(self.h, v), "sw_profile")
 
     KERNELS = ("element_start", "element_stage", "element_final", "face", "element_general", "element_tracer",
-               "element_tracer_final")
+               "element_tracer_final", "reactions")
 
     def kernel_times(self):
         """{kernel class: (total ms, launches)} accumulated while profiling."""

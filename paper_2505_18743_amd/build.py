@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswdg.so")
 
 SOURCES = ["sw_api.hip", "sw_ens.hip", "sw_setup.hip", "sw_face.hip", "sw_stage_r1.hip", "sw_stage_r2.hip",
-           "sw_stage_r3.hip", "sw_tracer_r1.hip", "sw_tracer_r2.hip", "sw_tracer_r3.hip", "sw_vjp_r1.hip", "sw_vjp_r2.hip", "sw_vjp_r3.hip", "sw_vjp_face.hip", "sw_amr.hip"]
+           "sw_stage_r3.hip", "sw_tracer_r1.hip", "sw_tracer_r2.hip", "sw_tracer_r3.hip", "sw_vjp_r1.hip", "sw_vjp_r2.hip", "sw_vjp_r3.hip", "sw_vjp_face.hip", "sw_amr.hip", "sw_react.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          # multiply-adds fuse where the source writes them as one expression,

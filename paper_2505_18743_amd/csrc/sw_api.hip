@@ -430,7 +430,7 @@ struct sw_ctx {
   std::vector<std::pair<void*, size_t>> allocs;   // device blocks and their sizes
   // kernel timing (sw_profile): events recorded around each launch group
   bool prof = false;
-  int prof_mask = 0x7F;      // kernel classes timed while profiling
+  int prof_mask = 0xFF;      // kernel classes timed while profiling
   struct Ev { int kind; int nlaunch; hipEvent_t a, b; };
   std::vector<Ev> ev;
   double prof_ms[8]{};
@@ -2037,7 +2037,11 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
   return st;
 }
 
-sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
+}  // extern "C"
+
+namespace {
+
+sw_status check_tracer_list(const sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
   if (!flow) return fail(SW_EINVAL, "NULL flow context");
   if (n < 0 || (n > 0 && !tracers)) return fail(SW_EINVAL, "bad tracer context list");
   if (!(dt > 0.0)) return fail(SW_EINVAL, "sw_step_tracers needs a fixed dt > 0");
@@ -2049,13 +2053,121 @@ sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, doubl
         t->ci != flow->ci || t->cj != flow->cj || t->cdx != flow->cdx || t->dev != flow->dev)
       return fail(SW_EINVAL, "tracer context " + std::to_string(i) + ": mesh, degree or scheme differ from the flow's");
   }
+  return SW_OK;
+}
+
+// Records one step of the flow context with the fixed dt: the flow of every
+// stage and of the step's end into the context's record buffer.
+sw_status record_flow(sw_ctx* flow, double dt, double** stages, double** end) {
   const size_t KN = (size_t)flow->K * flow->NP;
   sw_status st = SW_OK;
   if (!flow->d_trec && (st = flow->alloc(&flow->d_trec, (size_t)(flow->ns + 1) * 3 * KN)) != SW_OK) return st;
   if (!flow->ev_rec) HIPCHK(hipEventCreateWithFlags(&flow->ev_rec, hipEventDisableTiming));
-  double* stages = flow->d_trec;
-  double* end = flow->d_trec + (size_t)flow->ns * 3 * KN;
-  if ((st = sw_step_record(flow, dt, stages, end)) != SW_OK) return st;
+  *stages = flow->d_trec;
+  *end = flow->d_trec + (size_t)flow->ns * 3 * KN;
+  return sw_step_record(flow, dt, *stages, *end);
+}
+
+// R_k of residual slot `slot` += sum_j B_kj int h c_j psi_i for the tracer
+// contexts' stage state (stage = the stage state, else the step's state),
+// on the flow's stream (every tracer context runs there during the call);
+// the contexts carry the same flow and bathymetry, so the depth is the first
+// context's
+sw_status add_reactions(sw_ctx* const* tr, int n, const double* B, int slot, bool stage) {
+  sw_ctx* c0 = tr[0];
+  const size_t KN = (size_t)c0->K * c0->NP;
+  for (const auto& L : c0->lv) {
+    const LevelTabs& t = c0->nv > 0 ? L.vtabs : L.tabs;
+    ReactArgs a{};
+    a.l = t.l;
+    a.w = t.w;
+    a.n = t.S;
+    a.N1 = c0->N1;
+    a.cell0 = L.cell0;
+    a.ncell = L.ncell;
+    a.M = n;
+    a.cdx = c0->d_cdx;
+    a.z = stage ? c0->d_ss[0] : c0->d_sn[0];
+    a.zb = c0->d_zb + (c0->nv > 0 ? L.voff : L.off);
+    for (int j = 0; j < n; ++j) {
+      const sw_ctx* c = tr[j];
+      a.c[j] = stage ? c->d_ss[3] : c->d_sn[3];
+      a.res[j] = c->d_res + ((size_t)slot * 4 + 3) * KN;
+    }
+    for (int i = 0; i < n * n; ++i) a.B[i] = B[i];
+    sw_ctx::Scope sc(tr[0], 7, 1);
+    HIPCHK(launch_react(c0->r, a, c0->s));
+  }
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, const double* react, double dt) {
+  if (!react) return sw_step_tracers(flow, n, tracers, dt);
+  sw_status st = check_tracer_list(flow, n, tracers, dt);
+  if (st != SW_OK) return st;
+  if (n < 1 || n > kMaxReact)
+    return fail(SW_EINVAL, "sw_step_tracers_react couples 1 to " + std::to_string(kMaxReact) + " tracer contexts");
+  for (int i = 0; i < n * n; ++i)
+    if (!std::isfinite(react[i])) return fail(SW_EINVAL, "reaction matrix entry " + std::to_string(i) + " is not finite");
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (tracers[i] == tracers[j]) return fail(SW_EINVAL, "tracer context " + std::to_string(i) + " is listed twice");
+  double *stages = nullptr, *end = nullptr;
+  if ((st = record_flow(flow, dt, &stages, &end)) != SW_OK) return st;
+  // every launch of the tracers goes to the flow's stream for the call, after
+  // the tracers' earlier work; their own streams wait for the call's end
+  std::vector<hipStream_t> own(n);
+  for (int i = 0; i < n; ++i) {
+    sw_ctx* t = tracers[i];
+    if (t->s != flow->s) {
+      if (!t->ev_rec) HIPCHK(hipEventCreateWithFlags(&t->ev_rec, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(t->ev_rec, t->s));
+      HIPCHK(hipStreamWaitEvent(flow->s, t->ev_rec, 0));
+    }
+  }
+  for (int i = 0; i < n; ++i) own[i] = ctx_swap_stream(tracers[i], flow->s);
+  const size_t KN = (size_t)flow->K * flow->NP;
+  auto point = [&](sw_ctx* t, const double* base) {
+    for (int f = 0; f < 3; ++f) t->rp[f] = base ? base + f * KN : nullptr;
+  };
+  // stage by stage over the tracers: the reactions of a stage need every
+  // tracer's state of that stage
+  for (int i = 0; i < n && st == SW_OK; ++i) {
+    point(tracers[i], nullptr);
+    st = sw_step_begin(tracers[i], dt);
+  }
+  if (st == SW_OK) st = add_reactions(tracers, n, react, 0, false);
+  for (int l = 2; l <= flow->ns && st == SW_OK; ++l) {
+    for (int i = 0; i < n && st == SW_OK; ++i) {
+      point(tracers[i], stages + (size_t)(l - 1) * 3 * KN);
+      st = sw_rk_stage(tracers[i], l);
+    }
+    if (st == SW_OK) st = add_reactions(tracers, n, react, l - 1, true);
+  }
+  for (int i = 0; i < n && st == SW_OK; ++i) {
+    point(tracers[i], end);
+    st = sw_step_end(tracers[i]);
+  }
+  for (int i = 0; i < n; ++i) {
+    point(tracers[i], nullptr);
+    (void)ctx_swap_stream(tracers[i], own[i]);
+  }
+  if (st != SW_OK) return st;
+  HIPCHK(hipEventRecord(flow->ev_rec, flow->s));
+  for (int i = 0; i < n; ++i)
+    if (own[i] != flow->s) HIPCHK(hipStreamWaitEvent(own[i], flow->ev_rec, 0));
+  return SW_OK;
+}
+
+sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
+  sw_status st = check_tracer_list(flow, n, tracers, dt);
+  if (st != SW_OK) return st;
+  double *stages = nullptr, *end = nullptr;
+  if ((st = record_flow(flow, dt, &stages, &end)) != SW_OK) return st;
   HIPCHK(hipEventRecord(flow->ev_rec, flow->s));
   for (int i = 0; i < n; ++i) {
     sw_ctx* t = tracers[i];
@@ -2972,13 +3084,13 @@ sw_status sw_get_workgroup(const sw_ctx* c, int32_t level, int32_t kernel, int32
 sw_status sw_profile(sw_ctx* c, int32_t on) {
   if (!c) return fail(SW_EINVAL, "NULL context");
   c->prof = on != 0;
-  c->prof_mask = on > 1 ? (on >> 1) & 0x7F : 0x7F;
+  c->prof_mask = on > 1 ? (on >> 1) & 0xFF : 0xFF;
   return SW_OK;
 }
 
 sw_status sw_kernel_time(sw_ctx* c, int32_t kind, double* ms_total, int64_t* launches) {
   if (!c || !ms_total || !launches) return fail(SW_EINVAL, "NULL argument");
-  if (kind < 0 || kind > 6) return fail(SW_EINVAL, "kind must be 0..6");
+  if (kind < 0 || kind > 7) return fail(SW_EINVAL, "kind must be 0..7");
   for (auto& e : c->ev) {
     HIPCHK(hipEventSynchronize(e.b));
     float ms = 0.0f;

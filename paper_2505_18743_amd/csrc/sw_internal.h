@@ -229,6 +229,23 @@ struct AmrMassArgs {
   double* out;           // [K][2]: int h, int z_b l
 };
 hipError_t launch_amr_eta(const AmrEtaArgs& a, hipStream_t s);
+// linear reactions coupling tracers: R_k += sum_j B_kj int h c_j psi_i on the
+// volume rule, for the stage state of every tracer context (the contexts
+// share the flow, so the depth comes from the first one)
+constexpr int kMaxReact = 8;
+constexpr int kReactMaxRule = 32;   // volume-rule nodes per direction
+struct ReactArgs {
+  const double* l;       // [n][N1] basis values at the volume rule's nodes
+  const double* w;       // [n] the rule's weights on [0, 1]
+  int n, N1, cell0, ncell, M;
+  const double* cdx;     // [K]
+  const double* z;       // zeta of the stage state [K][NP]
+  const double* zb;      // level block of depth samples [ncell][n(a)][n(b)]
+  const double* c[kMaxReact];    // tracer context j: concentration of the stage state [K][NP]
+  double* res[kMaxReact];        // tracer context k: the stage's residual R [K][NP] (added to)
+  double B[kMaxReact * kMaxReact];   // B_kj at [k * M + j]
+};
+hipError_t launch_react(int r, const ReactArgs& a, hipStream_t s);
 hipError_t launch_amr_transfer(const AmrXferArgs& a, hipStream_t s);
 hipError_t launch_amr_raster(const RasterArgs& a, hipStream_t s);
 hipError_t launch_amr_mass(const AmrMassArgs& a, hipStream_t s);

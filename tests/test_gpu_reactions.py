@@ -1,0 +1,153 @@
+"""GPU: tracers that react with each other (sw_step_tracers_react: the
+source h phi_k(c_1, ..., c_M) of eq:shw with phi_k = sum_j B_kj c_j, taken
+explicitly in every stage as eq:imex_shw takes it) against the oracle's
+stage-by-stage coupled step (oracle.step_coupled).
+
+* 12 steps of three tracers on the hanging quadtree with wet/dry cells, tide
+  and Manning friction (r = 2, SSP3; r = 1, IMEX), with a non-symmetric B
+  that converts and feeds back, and one tracer with its own diffusion and
+  decay: every tracer within the step tolerance of the oracle's;
+* the same with the paper's quadrature (Table 1), whose volume rule carries
+  the reaction integrals;
+* B = 0 equals sw_step_tracers bit for bit (the stage-by-stage order
+  changes nothing else), and the flow context's own state is untouched by
+  the reactions;
+* argument checks: more than eight tracers, a context listed twice, a
+  non-finite entry.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import step_coupled
+from test_gpu_parity import TOL_STEP, cpu, gpu_from_oracle, hanging_case, rel
+from test_gpu_paper_quadrature import coastal_paper
+from test_gpu_tracer_replay import fixed_dt
+from test_gpu_tracer_sources import with_sources
+
+pytestmark = pytest.mark.gpu
+
+BASE = np.array([[-1.0, 0.0, 0.3],
+                 [0.8, -0.5, 0.0],
+                 [0.2, 0.5, -0.3]])
+SOURCES = [dict(tracer_diff=0.33, tracer_strain=0.004, tracer_decay=1e-4), dict(), dict()]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def inits(o):
+    d = o.dof_coords()
+    x, y = d[..., 0], d[..., 1]
+    return [np.where(x < 1300.0, 1.0, 0.25) + 0.1 * np.sin(y / 200.0),
+            0.5 + 0.3 * np.cos(x / 300.0),
+            0.2 + 0.1 * np.sin((x + y) / 250.0)]
+
+
+def run_pair(make, nsteps=12, rk=None):
+    o, b = make()
+    if rk:
+        o.p.rk = rk
+    st0 = o.get_state()
+    flow = gpu_from_oracle(o, b)
+    dt = fixed_dt(flow, st0)
+    B = BASE * (0.02 / dt)           # a few per cent of each tracer reacts per step
+    cs = inits(o)
+    oracles, ctxs = [], []
+    for src, c in zip(SOURCES, cs):
+        oi, _ = make()
+        if rk:
+            oi.p.rk = rk
+        with_sources(oi, **src)
+        ctxs.append(gpu_from_oracle(oi, b))
+        oi.set_state(st0[0], st0[1], st0[2], c)
+        oracles.append(oi)
+    flow.set_state(*st0)
+    flow.set_time(0.0)
+    for t, c in zip(ctxs, cs):
+        t.set_state(st0[0], st0[1], st0[2], c)
+        t.set_time(0.0)
+    for _ in range(nsteps):
+        flow.step_tracers_react(ctxs, B, dt)
+        step_coupled(oracles, B, dt)
+    flow.sync()
+    K = o.m.K
+    for k, (t, oi) in enumerate(zip(ctxs, oracles)):
+        got = t.get_state()
+        e = rel(cpu(got[3], K), oi.adapted_state()[3])
+        moved = rel(cpu(got[3], K), np.asarray(cs[k]))
+        say(f"  tracer {k}: rel err vs oracle {e:.3e} (change over the run {moved:.3e})")
+        assert e < TOL_STEP, (k, e)
+        assert moved > 1e-2
+        t.close()
+    flow.close()
+
+
+def test_reacting_tracers_ssp3_r2():
+    say("case: 3 reacting tracers, hanging mesh r=2 S=(16,8), SSP3, 12 steps")
+    run_pair(lambda: hanging_case(2, (16, 8)))
+
+
+def test_reacting_tracers_imex_r1():
+    say("case: 3 reacting tracers, hanging mesh r=1 S=(8,4), IMEX, 12 steps")
+    run_pair(lambda: hanging_case(1, (8, 4)), rk="imex")
+
+
+def test_reacting_tracers_paper_quadrature():
+    say("case: 3 reacting tracers, paper quadrature r=2, SSP3, 8 steps")
+    run_pair(lambda: coastal_paper(2), nsteps=8)
+
+
+def test_zero_reactions_equal_step_tracers():
+    say("case: B = 0 equals sw_step_tracers bit for bit, 6 steps")
+    o, b = hanging_case(2, (16, 8))
+    st0 = o.get_state()
+    cs = inits(o)
+    results = []
+    for react in (True, False):
+        flow = gpu_from_oracle(o, b)
+        dt = fixed_dt(flow, st0)
+        ctxs = []
+        for src, c in zip(SOURCES, cs):
+            oi, _ = hanging_case(2, (16, 8))
+            t = gpu_from_oracle(with_sources(oi, **src), b)
+            t.set_state(st0[0], st0[1], st0[2], c)
+            t.set_time(0.0)
+            ctxs.append(t)
+        flow.set_state(*st0)
+        flow.set_time(0.0)
+        for _ in range(6):
+            if react:
+                flow.step_tracers_react(ctxs, np.zeros((3, 3)), dt)
+            else:
+                flow.step_tracers(ctxs, dt)
+        flow.sync()
+        results.append(([t.get_state() for t in ctxs], flow.get_state()))
+        for t in ctxs:
+            t.close()
+        flow.close()
+    (a, fa), (b_, fb) = results
+    for f in range(4):
+        assert torch.equal(fa[f], fb[f]), f
+    for ga, gb in zip(a, b_):
+        for f in range(4):
+            assert torch.equal(ga[f], gb[f]), f
+
+
+def test_react_argument_checks():
+    say("case: sw_step_tracers_react argument checks")
+    o, b = hanging_case(1, (8, 4))
+    flow = gpu_from_oracle(o, b)
+    t1 = gpu_from_oracle(hanging_case(1, (8, 4))[0], b)
+    dt = 1.0
+    with pytest.raises(RuntimeError, match="twice"):
+        flow.step_tracers_react([t1, t1], np.zeros((2, 2)), dt)
+    with pytest.raises(RuntimeError, match="not finite"):
+        flow.step_tracers_react([t1], np.array([[np.nan]]), dt)
+    with pytest.raises(RuntimeError, match="1 to 8"):
+        flow.step_tracers_react([t1] * 9, np.zeros((9, 9)), dt)
+    with pytest.raises(RuntimeError, match="flow"):
+        flow.step_tracers_react([flow], np.zeros((1, 1)), dt)
+    t1.close()
+    flow.close()
