@@ -419,6 +419,10 @@ struct sw_ctx {
   bool ghost_set = false;
   int *d_cfoff = nullptr, *d_cfent = nullptr;
   bool start_ready = false;   // H^n, stage-1 volume terms and degrees of the current state are in place
+  // the prepared start came from a tracer replay's final kernel, which left
+  // the flow's volume terms out (a coupled step prepares it again)
+  bool start_replay = false;
+  bool replaying = false;     // inside a tracer replay (sw_tracer_step, sw_step_tracers_react)
   const double* rp[3] = {nullptr, nullptr, nullptr};   // tracer replay: recorded flow of the current stage
   double* d_trec = nullptr;   // sw_step_tracers: the flow record of one step ([ns][3][KN] stages, [3][KN] end)
   hipEvent_t ev_rec = nullptr;  // sw_step_tracers: the record is complete / the tracers are done with it
@@ -1928,8 +1932,9 @@ sw_status sw_step_begin(sw_ctx* c, double dt) {
   }
   // degree adaptation, H(zeta^n) and stage-1 volume terms (already in place after
   // a previous step's final kernel)
-  if (!c->start_ready)
+  if (!c->start_ready || (c->start_replay && !c->replaying))
     if ((st = elements(c, F_START, M_START, -1, 0, 0, nullptr, 0, 0)) != SW_OK) return st;
+  c->start_replay = false;
   const double* stn[4] = {c->d_sn[0], c->d_sn[1], c->d_sn[2], c->d_sn[3]};
   if ((st = faces(c, stn, c->c[0], 0)) != SW_OK) return st;
   if (!c->fixed_dt)
@@ -1974,6 +1979,7 @@ sw_status sw_step_end(sw_ctx* c) {
   HIPCHK(hipGetLastError());
   c->stage_done = 0;
   c->start_ready = true;
+  c->start_replay = c->rp[0] != nullptr;
   ++c->nstep;
   return SW_OK;
 }
@@ -2023,8 +2029,8 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
     for (int f = 0; f < 3; ++f) c->rp[f] = base ? base + f * KN : nullptr;
   };
   point(nullptr);
+  c->replaying = true;
   sw_status st = sw_step_begin(c, dt);
-  if (st != SW_OK) return st;
   for (int l = 2; l <= c->ns && st == SW_OK; ++l) {
     point(stages + (size_t)(l - 1) * 3 * KN);
     st = sw_rk_stage(c, l);
@@ -2034,6 +2040,7 @@ sw_status sw_tracer_step(sw_ctx* c, const double* stages, const double* end, dou
     st = sw_step_end(c);
   }
   point(nullptr);
+  c->replaying = false;
   return st;
 }
 
@@ -2129,7 +2136,10 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
       HIPCHK(hipStreamWaitEvent(flow->s, t->ev_rec, 0));
     }
   }
-  for (int i = 0; i < n; ++i) own[i] = ctx_swap_stream(tracers[i], flow->s);
+  for (int i = 0; i < n; ++i) {
+    own[i] = ctx_swap_stream(tracers[i], flow->s);
+    tracers[i]->replaying = true;
+  }
   const size_t KN = (size_t)flow->K * flow->NP;
   auto point = [&](sw_ctx* t, const double* base) {
     for (int f = 0; f < 3; ++f) t->rp[f] = base ? base + f * KN : nullptr;
@@ -2154,6 +2164,7 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
   }
   for (int i = 0; i < n; ++i) {
     point(tracers[i], nullptr);
+    tracers[i]->replaying = false;
     (void)ctx_swap_stream(tracers[i], own[i]);
   }
   if (st != SW_OK) return st;
