@@ -132,6 +132,9 @@ typedef struct {
   double dt;                 /* time step of the last step                              */
   double t;                  /* model time                                              */
   int64_t n_pos_viol;        /* (cell, stage) pairs with negative target mass           */
+                             /* (a tracer replay forms no flow target: min_target_mass  */
+                             /* is 1e300 and n_pos_viol 0 there; the flow's are the     */
+                             /* recording context's)                                    */
   int32_t max_newton_it;     /* largest Newton iteration count in the last step          */
   int32_t nonfinite;         /* 1 if a non-finite value was found in the state           */
   int64_t n_r0_cells;        /* cells at degree 0 for the next step (the degree decision  */

@@ -958,9 +958,13 @@ sw_status reduce_dt(sw_ctx* c, const double* mcfl, double* dst) {
 sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nterm, const double* coef, int diag_init,
                    int kind, const double* coeft = nullptr, double att = 0.0) {
   // a tracer replay, and the volume terms on a rule of their own, run the
-  // general kernel on every cell
+  // general kernel on every cell; a replay's stages (no degree decision or
+  // remap) run the fast tracer kernel on every cell, with the flow from the
+  // record
   const bool tracer = c->p.tracer != 0;
-  const bool fast_ok = !(tracer && c->rp[0] != nullptr) && c->nv == 0;
+  const bool replay = tracer && c->rp[0] != nullptr;
+  const bool fast_ok = !replay && c->nv == 0;
+  const bool trc_replay = replay && fmode == F_STAGE && c->nv == 0;
   if (fast_ok && tracer && fmode == F_FINAL) {
     // the final kernel updates the degree flags; the tracer kernel reads the step's own
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
@@ -989,6 +993,13 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
       StageArgs tr = a;
       tr.need = c->d_need;
       HIPCHK(launch_trc(c->r, L.P, fmode, tr, L.nblk, c->s));
+    }
+    if (trc_replay) {
+      sw_ctx::Scope sc(c, 5, 1);
+      StageArgs tr = a;
+      tr.need = nullptr;   // every cell
+      HIPCHK(launch_trc(c->r, L.P, F_STAGE, tr, L.nblk, c->s));
+      continue;
     }
     StageArgs g = a;
     g.need = fast_ok ? c->d_need : nullptr;

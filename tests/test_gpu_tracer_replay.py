@@ -69,6 +69,8 @@ def test_replay_equals_coupled_and_oracle(rk):
     da, db = rep.diagnostics(), rec.diagnostics()
     assert da["t"] == db["t"] and da["dt"] == db["dt"]
     assert da["total_mass"] == pytest.approx(db["total_mass"], rel=1e-13)
+    # a replay forms no flow target and takes no Newton step
+    assert da["n_pos_viol"] == 0 and da["min_target_mass"] == 1e300 and da["max_newton_it"] == 0
     # a second tracer over the same record equals its coupled run
     dof = o.dof_coords()
     c1 = np.where(dof[..., 0] < 1300.0, 1.0, 0.25) + 0.1 * np.sin(dof[..., 1] / 200.0)
