@@ -904,6 +904,7 @@ FaceArgs face_args(sw_ctx* c, int dir, int second, int q, const double* const* s
   a.g = c->p.g;
   a.eps = c->p.eps;
   a.tracer = c->p.tracer ? 1 : 0;
+  a.tonly = (c->p.tracer && c->replaying) ? 1 : 0;
   a.gof = c->d_gof;
   a.ghost = c->d_ghost;
   a.ng = c->ng;

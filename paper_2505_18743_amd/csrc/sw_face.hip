@@ -21,9 +21,13 @@ __device__ __forceinline__ int row_dof(int side, int k) {
   return side == 0 ? k * N1 : side == 1 ? k * N1 + R : side == 2 ? k : R * N1 + k;
 }
 
+// NQ: 3 (flow), 4 (flow and tracer), or 1: the tracer's terms only, from the
+// traces of all four fields (a tracer replay, whose flow is given)
 template <int R, int Q, int NQ>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 3 : 2))) void k_face(FaceArgs A) {
   constexpr int N1 = R + 1, NP = N1 * N1, FPB = kWave / Q;
+  constexpr bool TO = NQ == 1;
+  constexpr int NL = TO ? 4 : NQ;   // fields whose traces are read
   const int tid = threadIdx.x, lane = tid % Q, lf = tid / Q;
   const int bl = A.xmap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   // segment of this workgroup (uniform); a single-segment launch (one level)
@@ -49,18 +53,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
   const bool act = fv && ok;
   if (!ok) cA = cB = 0;
   if (bnd) cB = cA;
-  constexpr int nq = NQ;   // fields: zeta, qx, qy (+ tracer)
-
   // face-row coefficients of both sides (GLL support points include the end
   // points, so each trace is the 1-D interpolant of that row)
-  double cfA[NQ][N1], cfB[NQ][N1];
+  double cfA[NL][N1], cfB[NL][N1];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int q = 0; q < NL; ++q)
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const bool use = q < nq;
-      cfA[q][k] = use ? A.st[q][(size_t)cA * NP + row_dof<R>(sA, k)] : 0.0;
-      cfB[q][k] = use ? A.st[q][(size_t)cB * NP + row_dof<R>(sB, k)] : 0.0;
+      cfA[q][k] = A.st[q][(size_t)cA * NP + row_dof<R>(sA, k)];
+      cfB[q][k] = A.st[q][(size_t)cB * NP + row_dof<R>(sB, k)];
     }
   const double nx = sA == 0 ? -1.0 : (sA == 1 ? 1.0 : 0.0);
   const double ny = sA == 2 ? -1.0 : (sA == 3 ? 1.0 : 0.0);
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
     }
     double vA[4] = {0.0, 0.0, 0.0, 0.0}, vB[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NL; ++q) {
       double sa = 0.0, sb = 0.0;
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
@@ -165,8 +166,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
-        pA[q][k] += wl * cAv[q] * la[k];
-        pB[q][k] += wl * cBv[q] * lb[k];
+        pA[q][k] += wl * cAv[TO ? 3 : q] * la[k];
+        pB[q][k] += wl * cBv[TO ? 3 : q] * lb[k];
       }
     lmax = fmax(lmax, lam);
   }
@@ -193,8 +194,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
   for (int e = 0; e < PER; ++e) {
     const int ia = lane * PER + e;
     const int iq = ia < NE ? ia / N1 : 0, ik = ia < NE ? ia % N1 : 0;
-    pa[e] = rA + (size_t)iq * KN + row_dof<R>(sA, ik);
-    pb[e] = rB + (size_t)iq * KN + row_dof<R>(sB, ik);
+    const int fq = TO ? 3 : iq;   // the residual field of entry ia
+    pa[e] = rA + (size_t)fq * KN + row_dof<R>(sA, ik);
+    pb[e] = rB + (size_t)fq * KN + row_dof<R>(sB, ik);
     oa[e] = *pa[e];      // in range for every lane (clamped entry); used only if owned
     ob[e] = *pb[e];
   }
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R <= 2 ? 
 
 template <int R, int Q>
 static hipError_t face_rq(const FaceArgs& a, int nblk, hipStream_t s) {
-  if (a.tracer) hipLaunchKernelGGL((k_face<R, Q, 4>), dim3(nblk), dim3(kWave), 0, s, a);
+  if (a.tracer && a.tonly) hipLaunchKernelGGL((k_face<R, Q, 1>), dim3(nblk), dim3(kWave), 0, s, a);
+  else if (a.tracer) hipLaunchKernelGGL((k_face<R, Q, 4>), dim3(nblk), dim3(kWave), 0, s, a);
   else hipLaunchKernelGGL((k_face<R, Q, 3>), dim3(nblk), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }

@@ -126,6 +126,7 @@ struct FaceArgs {
   int* err;
   double g, eps;
   int tracer;
+  int tonly;             // 1: the tracer's face terms only (a tracer replay: the flow is given)
   int xmap;              // 1: each XCD takes one contiguous range of the class's faces
 };
 
