@@ -34,6 +34,50 @@ __device__ __forceinline__ int partner_i(int v) {
   else if constexpr (M == 8) return dpp_i<0x140>(v);
   else return __shfl_xor(v, M);
 }
+// Lane k's value (k a constant once the caller's loop is unrolled) to every
+// lane of its group of P: the DPP broadcast of a row lane (P = 16) or of a
+// quad lane (P = 4), a ds_bpermute otherwise.
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  return dpp_d<0x150 + K>(v);   // row_newbcast:K
+}
+template <int K>
+__device__ __forceinline__ double quad_bcast(double v) {
+  return dpp_d<K | (K << 2) | (K << 4) | (K << 6)>(v);   // quad_perm(K,K,K,K)
+}
+template <int P>
+__device__ __forceinline__ double gbcast(double v, int k) {
+  if constexpr (P == 16) {
+    switch (k) {
+      case 0: return row_bcast<0>(v);
+      case 1: return row_bcast<1>(v);
+      case 2: return row_bcast<2>(v);
+      case 3: return row_bcast<3>(v);
+      case 4: return row_bcast<4>(v);
+      case 5: return row_bcast<5>(v);
+      case 6: return row_bcast<6>(v);
+      case 7: return row_bcast<7>(v);
+      case 8: return row_bcast<8>(v);
+      case 9: return row_bcast<9>(v);
+      case 10: return row_bcast<10>(v);
+      case 11: return row_bcast<11>(v);
+      case 12: return row_bcast<12>(v);
+      case 13: return row_bcast<13>(v);
+      case 14: return row_bcast<14>(v);
+      default: return row_bcast<15>(v);
+    }
+  } else if constexpr (P == 4) {
+    switch (k) {
+      case 0: return quad_bcast<0>(v);
+      case 1: return quad_bcast<1>(v);
+      case 2: return quad_bcast<2>(v);
+      default: return quad_bcast<3>(v);
+    }
+  } else {
+    return __shfl(v, k, P);
+  }
+}
+
 // Ordering point for LDS data exchanged inside one wavefront (the wave's LDS
 // operations complete in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_sync() {
