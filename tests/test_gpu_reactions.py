@@ -12,6 +12,8 @@ stage-by-stage coupled step (oracle.step_coupled).
 * B = 0 equals sw_step_tracers bit for bit (the stage-by-stage order
   changes nothing else), and the flow context's own state is untouched by
   the reactions;
+* the largest set the call takes (eight tracers, a random B) and a single
+  tracer reacting with itself, against the oracle;
 * argument checks: more than eight tracers, a context listed twice, a
   non-finite entry.
 """
@@ -97,6 +99,42 @@ def test_reacting_tracers_imex_r1():
 def test_reacting_tracers_paper_quadrature():
     say("case: 3 reacting tracers, paper quadrature r=2, SSP3, 8 steps")
     run_pair(lambda: coastal_paper(2), nsteps=8)
+
+
+def test_eight_reacting_tracers_and_one():
+    say("case: the largest set (8 reacting tracers) and a single tracer reacting with itself, r=1, 4 steps")
+    o, b = hanging_case(1, (8, 4))
+    st0 = o.get_state()
+    flow = gpu_from_oracle(o, b)
+    dt = fixed_dt(flow, st0)
+    rng = np.random.default_rng(8)
+    d = o.dof_coords()
+    K = o.m.K
+    for M in (8, 1):
+        B = rng.uniform(-1.0, 1.0, (M, M)) * (0.02 / dt)
+        cs = [0.5 + 0.4 * np.sin((k + 1) * d[..., 0] / 500.0) * np.cos(d[..., 1] / 400.0) for k in range(M)]
+        oracles, ctxs = [], []
+        for c in cs:
+            oi, _ = hanging_case(1, (8, 4))
+            ctxs.append(gpu_from_oracle(oi, b))
+            oi.set_state(st0[0], st0[1], st0[2], c)
+            oracles.append(oi)
+        flow.set_state(*st0)
+        flow.set_time(0.0)
+        for t, c in zip(ctxs, cs):
+            t.set_state(st0[0], st0[1], st0[2], c)
+            t.set_time(0.0)
+        for _ in range(4):
+            flow.step_tracers_react(ctxs, B, dt)
+            step_coupled(oracles, B, dt)
+        flow.sync()
+        worst = 0.0
+        for t, oi in zip(ctxs, oracles):
+            worst = max(worst, rel(cpu(t.get_state()[3], K), oi.adapted_state()[3]))
+            t.close()
+        say(f"  M={M}: worst tracer rel err vs oracle {worst:.3e}")
+        assert worst < TOL_STEP
+    flow.close()
 
 
 def test_zero_reactions_equal_step_tracers():
