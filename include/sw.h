@@ -419,8 +419,10 @@ sw_status sw_step_tracers(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, doubl
  * stage.  The tracer contexts carry the flow's bathymetry and state, so that
  * depth is taken from the first of them.  Each context's own decay (params.tracer_decay) and diffusion still
  * apply.  Every launch of the call runs on the flow context's stream, after
- * the tracer contexts' earlier work; their streams wait for its end.  A
- * context listed twice, or the flow context itself, is SW_EINVAL. */
+ * the tracer contexts' earlier work; their streams wait for its end (also
+ * after a failure).  A context listed twice, the flow context itself, or
+ * tracer contexts of different quadrature (sw_params.quadrature) is
+ * SW_EINVAL. */
 sw_status sw_step_tracers_react(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, const double *react_host,
                                 double dt);
 

@@ -2132,9 +2132,13 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
     return fail(SW_EINVAL, "sw_step_tracers_react couples 1 to " + std::to_string(kMaxReact) + " tracer contexts");
   for (int i = 0; i < n * n; ++i)
     if (!std::isfinite(react[i])) return fail(SW_EINVAL, "reaction matrix entry " + std::to_string(i) + " is not finite");
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     for (int j = 0; j < i; ++j)
       if (tracers[i] == tracers[j]) return fail(SW_EINVAL, "tracer context " + std::to_string(i) + " is listed twice");
+    // the reaction integrals take the first context's volume rule
+    if (tracers[i]->nv != tracers[0]->nv)
+      return fail(SW_EINVAL, "tracer context " + std::to_string(i) + ": quadrature differs from the first context's");
+  }
   double *stages = nullptr, *end = nullptr;
   if ((st = record_flow(flow, dt, &stages, &end)) != SW_OK) return st;
   // every launch of the tracers goes to the flow's stream for the call, after
@@ -2179,11 +2183,11 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
     tracers[i]->replaying = false;
     (void)ctx_swap_stream(tracers[i], own[i]);
   }
-  if (st != SW_OK) return st;
+  // the tracers' streams wait for what the call launched, also after a failure
   HIPCHK(hipEventRecord(flow->ev_rec, flow->s));
   for (int i = 0; i < n; ++i)
     if (own[i] != flow->s) HIPCHK(hipStreamWaitEvent(own[i], flow->ev_rec, 0));
-  return SW_OK;
+  return st;
 }
 
 sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
