@@ -35,8 +35,9 @@ __device__ __forceinline__ int partner_i(int v) {
   else return __shfl_xor(v, M);
 }
 // Lane k's value (k a constant once the caller's loop is unrolled) to every
-// lane of its group of P: the DPP broadcast of a row lane (P = 16) or of a
-// quad lane (P = 4), a ds_bpermute otherwise.
+// lane of its group of P: the DPP broadcast of a row lane (P = 16; P = 8 takes
+// two and keeps its half-row's) or of a quad lane (P = 4), a ds_bpermute
+// otherwise.
 template <int K>
 __device__ __forceinline__ double row_bcast(double v) {
   return dpp_d<0x150 + K>(v);   // row_newbcast:K
@@ -66,6 +67,21 @@ __device__ __forceinline__ double gbcast(double v, int k) {
       case 14: return row_bcast<14>(v);
       default: return row_bcast<15>(v);
     }
+  } else if constexpr (P == 8) {
+    // a row broadcast reaches 16 lanes: lane k for the lower half-row, lane
+    // 8 + k for the upper
+    double lo, hi;
+    switch (k) {
+      case 0: lo = row_bcast<0>(v); hi = row_bcast<8>(v); break;
+      case 1: lo = row_bcast<1>(v); hi = row_bcast<9>(v); break;
+      case 2: lo = row_bcast<2>(v); hi = row_bcast<10>(v); break;
+      case 3: lo = row_bcast<3>(v); hi = row_bcast<11>(v); break;
+      case 4: lo = row_bcast<4>(v); hi = row_bcast<12>(v); break;
+      case 5: lo = row_bcast<5>(v); hi = row_bcast<13>(v); break;
+      case 6: lo = row_bcast<6>(v); hi = row_bcast<14>(v); break;
+      default: lo = row_bcast<7>(v); hi = row_bcast<15>(v); break;
+    }
+    return (__lane_id() & 8) ? hi : lo;
   } else if constexpr (P == 4) {
     switch (k) {
       case 0: return quad_bcast<0>(v);
