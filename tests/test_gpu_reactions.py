@@ -12,6 +12,8 @@ stage-by-stage coupled step (oracle.step_coupled).
 * B = 0 equals sw_step_tracers bit for bit (the stage-by-stage order
   changes nothing else), and the flow context's own state is untouched by
   the reactions;
+* tracer contexts on streams other than the flow's give the same tracers
+  bit for bit (the call orders them with events);
 * the largest set the call takes (eight tracers, a random B) and a single
   tracer reacting with itself, against the oracle;
 * argument checks: more than eight tracers, a context listed twice, a
@@ -171,6 +173,46 @@ def test_zero_reactions_equal_step_tracers():
     for ga, gb in zip(a, b_):
         for f in range(4):
             assert torch.equal(ga[f], gb[f]), f
+
+
+def test_reacting_tracers_on_streams_of_their_own():
+    say("case: 3 reacting tracers whose contexts live on two other streams and the flow's, 6 steps, "
+        "against all on the flow's stream")
+    o, b = hanging_case(2, (16, 8))
+    st0 = o.get_state()
+    cs = inits(o)
+    extra = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+
+    def run(streams):
+        flow = gpu_from_oracle(o, b)
+        dt = fixed_dt(flow, st0)
+        B = BASE * (0.02 / dt)
+        ctxs = []
+        for src, c, sm in zip(SOURCES, cs, streams):
+            with torch.cuda.stream(sm):
+                oi, _ = hanging_case(2, (16, 8))
+                t = gpu_from_oracle(with_sources(oi, **src), b)
+                t.set_state(st0[0], st0[1], st0[2], c)
+                t.set_time(0.0)
+            ctxs.append(t)
+        flow.set_state(*st0)
+        flow.set_time(0.0)
+        for _ in range(6):
+            flow.step_tracers_react(ctxs, B, dt)
+        out = []
+        for t, sm in zip(ctxs, streams):
+            with torch.cuda.stream(sm):
+                out.append(t.get_state()[3].clone())
+            sm.synchronize()
+            t.close()
+        flow.close()
+        return out
+
+    cur = torch.cuda.current_stream()
+    a = run([cur, cur, cur])
+    bb = run([extra[0], cur, extra[1]])
+    for k, (x, y) in enumerate(zip(a, bb)):
+        assert torch.equal(x, y), (k, float((x - y).abs().max()))
 
 
 def test_react_argument_checks():
