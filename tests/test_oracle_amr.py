@@ -15,6 +15,10 @@ conservative remap, eq:cons-remap, and the mass source Q^n, eq:mass-loss).
   more (brute force over all 2:1-balanced refinements of a small mesh); a
   merge that would break the balance is dropped; random flags on random
   quadtrees always give a balanced mesh that contains every flagged split.
+* Raster sampling: bilinear functions are reproduced exactly on a raster
+  with nx != ny and dx != dy (an i / j or x / y swap fails), raster nodes
+  give their values, and points outside take the value at the nearest point
+  of the raster (clamping per coordinate).
 * Q^n: over a fully wet lake on a rough raster bed, the change of total mass
   across a remesh equals the difference of the bathymetry integrals
   (eq:mass-loss), computed separately from the raster samples.
@@ -47,6 +51,31 @@ def interp_state(o, fz, fqx, fqy, fc=None):
     d = o.dof_coords()
     x, y = d[..., 0], d[..., 1]
     return [fz(x, y), fqx(x, y), fqy(x, y), fc(x, y) if fc else np.zeros_like(x)]
+
+
+def test_raster_sampling_is_bilinear_and_clamped():
+    rng = np.random.default_rng(7)
+    nx, ny, x0, y0, dx, dy = 7, 4, -3.0, 10.0, 2.5, 0.75
+    f = lambda x, y: 1.5 - 0.4 * x + 2.0 * y + 0.3 * x * y
+    X, Y = np.meshgrid(x0 + dx * np.arange(nx), y0 + dy * np.arange(ny))   # b[j, i]
+    grid = dict(x0=x0, y0=y0, dx=dx, dy=dy, b=f(X, Y))
+    # interior points: exact for a bilinear function
+    xy = np.stack([rng.uniform(x0, x0 + dx * (nx - 1), 200), rng.uniform(y0, y0 + dy * (ny - 1), 200)], axis=1)
+    assert np.allclose(sample_raster(grid, xy), f(xy[:, 0], xy[:, 1]), rtol=0.0, atol=1e-12)
+    # the raster's own nodes, the last row and column included
+    nodes = np.stack([X.ravel(), Y.ravel()], axis=1)
+    assert np.allclose(sample_raster(grid, nodes), grid["b"].ravel(), rtol=0.0, atol=1e-13)
+    # outside: the value at the nearest raster point, coordinate by coordinate
+    out = np.array([[x0 - 5.0, y0 + 1.1], [x0 + dx * (nx - 1) + 3.0, y0 - 2.0], [x0 + 4.2, y0 + dy * ny + 9.0]])
+    near = np.stack([np.clip(out[:, 0], x0, x0 + dx * (nx - 1)), np.clip(out[:, 1], y0, y0 + dy * (ny - 1))], axis=1)
+    assert np.allclose(sample_raster(grid, out), f(near[:, 0], near[:, 1]), rtol=0.0, atol=1e-12)
+    # a non-bilinear raster is matched at the nodes only: a point between
+    # nodes is the weighted mean of its four corners
+    b2 = rng.uniform(-1, 1, (ny, nx))
+    g2 = dict(grid, b=b2)
+    p = np.array([[x0 + 2.25 * dx, y0 + 1.5 * dy]])
+    want = 0.75 * 0.5 * b2[1, 2] + 0.25 * 0.5 * b2[1, 3] + 0.75 * 0.5 * b2[2, 2] + 0.25 * 0.5 * b2[2, 3]
+    assert abs(sample_raster(g2, p)[0] - want) <= 1e-14
 
 
 @pytest.mark.parametrize("quad", ["subgrid", "paper"])
