@@ -10,6 +10,8 @@ conservative remap, eq:cons-remap, and the mass source Q^n, eq:mass-loss).
   random points); merging the four children of a refined cell returns the
   cell's own coefficients; a merge keeps the integral of every field and
   leaves a residual orthogonal to Q_r of the parent (the L2 projection).
+* Per-cell scalars: refining and merging back returns them exactly; a
+  merge keeps their sum over the four children.
 * Criteria and 2:1 balance: one flagged cell gives exactly four children;
   flags next to coarse cells force the closure the balance needs and nothing
   more (brute force over all 2:1-balanced refinements of a small mesh); a
@@ -37,7 +39,7 @@ import torch
 from exact import G, Vortex
 from oracle import Mesh, Oracle, Params, gl_rule, tensor_basis
 from oracle.amr import (TRACER_GRAD, VORTICITY, indicator, plan, remesh, sample_raster, transfer,
-                        transfer_tables)
+                        transfer_cellwise, transfer_tables)
 from test_oracle_paper_quadrature import l2_errors, l2_project
 
 
@@ -181,6 +183,30 @@ def test_one_flag_gives_four_children():
     # ordered by level, then j, then i
     keys = list(zip(nm.level, nm.jj, nm.ii))
     assert keys == sorted(keys)
+
+
+def test_cell_values_survive_refine_and_merge():
+    # per-cell scalars (Manning, bed offset): children inherit, a parent takes
+    # the mean of its four children, so refining and merging back returns the
+    # original values exactly, and a merge of distinct values keeps their sum
+    m = Mesh.uniform(4, 3, 0.0, 0.0, 1.0)
+    vals = np.linspace(0.011, 0.04, m.K)
+    eta = np.zeros(m.K)
+    eta[[1, 6, 10]] = 1.0
+    nm, rel, nref, _, _ = plan(m, eta, 0.5, 0.0, 3)
+    assert nref == 3
+    v1 = transfer_cellwise(vals, rel)
+    # merge every refined cell back: children far below theta_c eta_max,
+    # n_max = 1 so that nothing refines
+    back, rel2, _, ncoa, _ = plan(nm, (nm.level == 0).astype(float), 0.5, 0.1, 1)
+    assert ncoa == 3 and back.K == m.K
+    assert np.array_equal(transfer_cellwise(v1, rel2), vals)
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.01, 0.05, nm.K)
+    w2 = transfer_cellwise(w, rel2)
+    for n, r_ in enumerate(rel2):
+        if r_[0] == "parent":
+            assert abs(4.0 * w2[n] - sum(w[k] for k in r_[1])) <= 1e-15
 
 
 def balanced(leaves, nx0, ny0):
