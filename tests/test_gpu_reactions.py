@@ -16,6 +16,8 @@ stage-by-stage coupled step (oracle.step_coupled).
   bit for bit (the call orders them with events);
 * the largest set the call takes (eight tracers, a random B) and a single
   tracer reacting with itself, against the oracle;
+* at full size (the 256x256 beach, the benchmark's launch configuration),
+  B = -kappa I equals each tracer context's own decay to 1e-12;
 * argument checks: more than eight tracers, a context listed twice, a
   non-finite entry.
 """
@@ -213,6 +215,59 @@ def test_reacting_tracers_on_streams_of_their_own():
     bb = run([extra[0], cur, extra[1]])
     for k, (x, y) in enumerate(zip(a, bb)):
         assert torch.equal(x, y), (k, float((x - y).abs().max()))
+
+
+def test_full_size_diagonal_reactions_are_each_tracers_decay():
+    say("case: beach_dambreak_256 at full size, 3 tracers, B = -kappa I against each context's own decay, 5 steps")
+    from paper_2505_18743_amd import Solver
+    from workloads import workload
+    wl = workload("beach_dambreak_256")
+    p = dict(wl["params"])
+    p["tracer"] = True
+    flow = Solver(wl["mesh"], wl["params"], device="cuda:0")
+    xy = flow.node_coords()
+    bed = wl["bed"](xy[:, 0], xy[:, 1])
+    dof = flow.dof_coords()
+    eta0 = wl["eta0"](dof[:, 0], dof[:, 1])
+
+    def ctx(pp):
+        s = Solver(wl["mesh"], pp, device="cuda:0")
+        s.set_bathymetry(bed)
+        s.set_manning(wl["manning"])
+        return s
+    flow.set_bathymetry(bed)
+    flow.set_manning(wl["manning"])
+    flow.init_lake_at_rest(eta0)
+    st0 = flow.get_state()
+    flow.step()
+    dt = float(flow.diagnostics()["dt"])
+    kappa = 0.01 / dt
+    x = (dof[:, 0] - dof[:, 0].min()) / np.ptp(dof[:, 0])
+    cs = [np.where(x < 0.5, 1.0, 0.2), 0.5 + 0.3 * np.cos(6.0 * x), 0.1 + 0.05 * np.sin(8.0 * x)]
+    pd = dict(p, tracer_decay=kappa)
+    results = []
+    for react in (True, False):
+        ctxs = [ctx(p if react else pd) for _ in cs]
+        flow.set_state(st0[0], st0[1], st0[2])
+        flow.set_time(0.0)
+        for t, c in zip(ctxs, cs):
+            t.set_state(st0[0], st0[1], st0[2], c)
+            t.set_time(0.0)
+        for _ in range(5):
+            if react:
+                flow.step_tracers_react(ctxs, -kappa * np.eye(3), dt)
+            else:
+                flow.step_tracers(ctxs, dt)
+        flow.sync()
+        results.append([t.get_state()[3].cpu().numpy() for t in ctxs])
+        for t in ctxs:
+            t.close()
+    flow.close()
+    for k, (a, b) in enumerate(zip(*results)):
+        e = rel(a, b)
+        moved = rel(b, cs[k])
+        say(f"  tracer {k}: reactions vs own decay rel diff {e:.3e} (change over the run {moved:.3e})")
+        assert e < 1e-12 and moved > 1e-3
 
 
 def test_react_argument_checks():
