@@ -2021,8 +2021,16 @@ sw_status sw_step_record(sw_ctx* c, double dt, double* stages, double* end) {
   if (st != SW_OK) return st;
   if ((st = sw_step_begin(c, dt)) != SW_OK) return st;
   for (int l = 2; l <= c->ns; ++l) {
-    if ((st = sw_rk_stage(c, l)) != SW_OK) return st;
-    if ((st = save(c->d_ss, l - 1)) != SW_OK) return st;
+    // the stage's kernels write its flow straight into the record (every
+    // cell's stage state is written by the stage, and read only within it)
+    double* own[3];
+    for (int f = 0; f < 3; ++f) {
+      own[f] = c->d_ss[f];
+      c->d_ss[f] = stages + ((size_t)(l - 1) * 3 + f) * KN;
+    }
+    st = sw_rk_stage(c, l);
+    for (int f = 0; f < 3; ++f) c->d_ss[f] = own[f];
+    if (st != SW_OK) return st;
   }
   const size_t KN3 = KN;
   for (int f = 0; f < 3; ++f) c->rec[f] = end ? end + f * KN3 : nullptr;
