@@ -100,6 +100,21 @@ hipError_t launch_trc(int r, int P, int mode, const StageArgs& a, int nblk, hipS
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_trc_multi_r1(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi_r2(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi_r3(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+
+hipError_t launch_trc_multi(int r, int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  if (ts.M < 1 || ts.M > kMaxReact) return hipErrorInvalidValue;
+  switch (r) {
+    case 1: return launch_trc_multi_r1(P, a, ts, nblk, s);
+    case 2: return launch_trc_multi_r2(P, a, ts, nblk, s);
+    case 3: return launch_trc_multi_r3(P, a, ts, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
 }  // namespace swk
 
 using namespace swk;
@@ -2128,29 +2143,79 @@ sw_status add_reactions(sw_ctx* const* tr, int n, const double* B, int slot, boo
   return SW_OK;
 }
 
-}  // namespace
+// One replayed stage l of the tracer contexts tr[0..n), whose flow pointers
+// name the record's stage: on the sample rule, one launch of the
+// multi-tracer kernel per level and group of at most kMaxReact contexts (the
+// matrix H(zeta^(l)) factorised once per cell for the group), then each
+// context's tracer face terms; otherwise each context's own sw_rk_stage.
+sw_status stage_tracers(sw_ctx* const* tr, int n, int l) {
+  sw_ctx* c0 = tr[0];
+  if (c0->nv > 0 || c0->rp[0] == nullptr) {
+    for (int i = 0; i < n; ++i) {
+      sw_status st = sw_rk_stage(tr[i], l);
+      if (st != SW_OK) return st;
+    }
+    return SW_OK;
+  }
+  if (l < 2 || l > c0->ns) return fail(SW_EINVAL, "stage index out of range");
+  for (int i = 0; i < n; ++i)
+    if (tr[i]->stage_done != l - 1) return fail(SW_EINVAL, "stages must be taken in order after sw_step_begin");
+  double coef[4];
+  for (int m = 0; m < 4; ++m) coef[m] = m < l - 1 ? c0->A[l - 1][m] : 0.0;
+  for (int g0 = 0; g0 < n; g0 += kMaxReact) {
+    const int gn = std::min(kMaxReact, n - g0);
+    sw_ctx* g = tr[g0];
+    for (const auto& L : g->lv) {
+      StageArgs a = stage_args(g, L);
+      a.slot = l - 1;
+      a.nterm = l - 1;
+      for (int m = 0; m < 4; ++m) a.a[m] = coef[m];
+      a.diag_init = l == 2 ? 1 : 0;
+      a.need = nullptr;   // every cell
+      TrcSet ts{};
+      ts.M = gn;
+      for (int j = 0; j < gn; ++j) {
+        const sw_ctx* c = tr[g0 + j];
+        ts.res[j] = c->d_res;
+        ts.cn[j] = c->d_cn;
+        ts.c0[j] = c->d_sn[3];
+        for (int f = 0; f < 4; ++f) ts.ss[j][f] = c->d_ss[f];
+        ts.cdiag[j] = c->d_cdiag;
+        ts.tnu[j] = c->p.tracer_diff * c->p.tracer_strain / (double)(c->r * c->r);
+        ts.tkap[j] = c->p.tracer_decay;
+      }
+      sw_ctx::Scope sc(g, 5, 1);
+      HIPCHK(launch_trc_multi(g->r, L.P, a, ts, L.nblk, g->s));
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    sw_ctx* c = tr[i];
+    const double* sts[4] = {c->d_ss[0], c->d_ss[1], c->d_ss[2], c->d_ss[3]};
+    sw_status st = faces(c, sts, c->c[l - 1], l - 1);
+    if (st != SW_OK) return st;
+    c->stage_done = l;
+  }
+  return SW_OK;
+}
 
-extern "C" {
-
-sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, const double* react, double dt) {
-  if (!react) return sw_step_tracers(flow, n, tracers, dt);
-  sw_status st = check_tracer_list(flow, n, tracers, dt);
-  if (st != SW_OK) return st;
-  if (n < 1 || n > kMaxReact)
-    return fail(SW_EINVAL, "sw_step_tracers_react couples 1 to " + std::to_string(kMaxReact) + " tracer contexts");
-  for (int i = 0; i < n * n; ++i)
-    if (!std::isfinite(react[i])) return fail(SW_EINVAL, "reaction matrix entry " + std::to_string(i) + " is not finite");
+// One step of the flow context recorded, then the tracer contexts stepped
+// stage by stage together over the record on the flow's stream (after their
+// earlier work; their streams wait for the call's launches), with the
+// reactions react (n x n, or NULL: none) added after each stage's residuals.
+sw_status step_tracers_impl(sw_ctx* flow, int n, sw_ctx* const* tracers, const double* react, double dt) {
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < i; ++j)
       if (tracers[i] == tracers[j]) return fail(SW_EINVAL, "tracer context " + std::to_string(i) + " is listed twice");
-    // the reaction integrals take the first context's volume rule
-    if (tracers[i]->nv != tracers[0]->nv)
+    // one launch steps several contexts: one quadrature and one degree rule
+    const sw_ctx* t = tracers[i];
+    if (t->nv != tracers[0]->nv)
       return fail(SW_EINVAL, "tracer context " + std::to_string(i) + ": quadrature differs from the first context's");
+    if (t->p.h_lim != tracers[0]->p.h_lim || (t->p.adapt_degree != 0) != (tracers[0]->p.adapt_degree != 0))
+      return fail(SW_EINVAL, "tracer context " + std::to_string(i) + ": degree adaptation differs from the first context's");
   }
   double *stages = nullptr, *end = nullptr;
-  if ((st = record_flow(flow, dt, &stages, &end)) != SW_OK) return st;
-  // every launch of the tracers goes to the flow's stream for the call, after
-  // the tracers' earlier work; their own streams wait for the call's end
+  sw_status st = record_flow(flow, dt, &stages, &end);
+  if (st != SW_OK || n == 0) return st;
   std::vector<hipStream_t> own(n);
   for (int i = 0; i < n; ++i) {
     sw_ctx* t = tracers[i];
@@ -2168,19 +2233,17 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
   auto point = [&](sw_ctx* t, const double* base) {
     for (int f = 0; f < 3; ++f) t->rp[f] = base ? base + f * KN : nullptr;
   };
-  // stage by stage over the tracers: the reactions of a stage need every
-  // tracer's state of that stage
+  // stage by stage over the tracers: a stage's reactions need every tracer's
+  // state of that stage, and one launch takes the stage of all of them
   for (int i = 0; i < n && st == SW_OK; ++i) {
     point(tracers[i], nullptr);
     st = sw_step_begin(tracers[i], dt);
   }
-  if (st == SW_OK) st = add_reactions(tracers, n, react, 0, false);
+  if (st == SW_OK && react) st = add_reactions(tracers, n, react, 0, false);
   for (int l = 2; l <= flow->ns && st == SW_OK; ++l) {
-    for (int i = 0; i < n && st == SW_OK; ++i) {
-      point(tracers[i], stages + (size_t)(l - 1) * 3 * KN);
-      st = sw_rk_stage(tracers[i], l);
-    }
-    if (st == SW_OK) st = add_reactions(tracers, n, react, l - 1, true);
+    for (int i = 0; i < n; ++i) point(tracers[i], stages + (size_t)(l - 1) * 3 * KN);
+    st = stage_tracers(tracers, n, l);
+    if (st == SW_OK && react) st = add_reactions(tracers, n, react, l - 1, true);
   }
   for (int i = 0; i < n && st == SW_OK; ++i) {
     point(tracers[i], end);
@@ -2198,24 +2261,25 @@ sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers,
   return st;
 }
 
+}  // namespace
+
+extern "C" {
+
+sw_status sw_step_tracers_react(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, const double* react, double dt) {
+  if (!react) return sw_step_tracers(flow, n, tracers, dt);
+  sw_status st = check_tracer_list(flow, n, tracers, dt);
+  if (st != SW_OK) return st;
+  if (n < 1 || n > kMaxReact)
+    return fail(SW_EINVAL, "sw_step_tracers_react couples 1 to " + std::to_string(kMaxReact) + " tracer contexts");
+  for (int i = 0; i < n * n; ++i)
+    if (!std::isfinite(react[i])) return fail(SW_EINVAL, "reaction matrix entry " + std::to_string(i) + " is not finite");
+  return step_tracers_impl(flow, n, tracers, react, dt);
+}
+
 sw_status sw_step_tracers(sw_ctx* flow, int32_t n, sw_ctx* const* tracers, double dt) {
   sw_status st = check_tracer_list(flow, n, tracers, dt);
   if (st != SW_OK) return st;
-  double *stages = nullptr, *end = nullptr;
-  if ((st = record_flow(flow, dt, &stages, &end)) != SW_OK) return st;
-  HIPCHK(hipEventRecord(flow->ev_rec, flow->s));
-  for (int i = 0; i < n; ++i) {
-    sw_ctx* t = tracers[i];
-    if (t->s != flow->s) HIPCHK(hipStreamWaitEvent(t->s, flow->ev_rec, 0));
-    if ((st = sw_tracer_step(t, stages, end, dt)) != SW_OK) return st;
-    // the next call's record waits for this replay
-    if (t->s != flow->s) {
-      if (!t->ev_rec) HIPCHK(hipEventCreateWithFlags(&t->ev_rec, hipEventDisableTiming));
-      HIPCHK(hipEventRecord(t->ev_rec, t->s));
-      HIPCHK(hipStreamWaitEvent(flow->s, t->ev_rec, 0));
-    }
-  }
-  return SW_OK;
+  return step_tracers_impl(flow, n, tracers, nullptr, dt);
 }
 
 }  // extern "C"

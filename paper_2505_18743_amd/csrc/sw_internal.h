@@ -247,6 +247,19 @@ struct ReactArgs {
   double B[kMaxReact * kMaxReact];   // B_kj at [k * M + j]
 };
 hipError_t launch_react(int r, const ReactArgs& a, hipStream_t s);
+// the tracer contexts of one replayed stage, stepped by one launch: the
+// first context's arrays are those of the StageArgs; all share the flow, the
+// mesh and the degree flags
+struct TrcSet {
+  int M;
+  double* res[kMaxReact];          // residual slots [NS][4][K][NP]
+  const double* cn[kMaxReact];     // C~^n [K][NP]
+  const double* c0[kMaxReact];     // c^n, the step start's tracer [K][NP]
+  double* ss[kMaxReact][4];        // stage state
+  double* cdiag[kMaxReact];        // per-cell diagnostics
+  double tnu[kMaxReact], tkap[kMaxReact];   // diffusion (C S / r^2) and decay
+};
+hipError_t launch_trc_multi(int r, int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
 hipError_t launch_amr_transfer(const AmrXferArgs& a, hipStream_t s);
 hipError_t launch_amr_raster(const RasterArgs& a, hipStream_t s);
 hipError_t launch_amr_mass(const AmrMassArgs& a, hipStream_t s);
