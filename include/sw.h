@@ -399,13 +399,18 @@ sw_status sw_tracer_step(sw_ctx *c, const double *stages_dev, const double *end_
 /* Several tracers (eq:shw with M > 1 passive tracers, each with its own
  * diffusion and decay): one step of the flow context with the fixed dt > 0,
  * recorded into buffers the flow context keeps (allocated on first use,
- * (s + 1) x 3 x n_dofs doubles), then sw_tracer_step of each of the n
- * tracer contexts over that record.  The tracer contexts must share the
- * flow's mesh, degree and scheme (SW_EINVAL otherwise) and start each call
- * with the flow's state, which sw_tracer_step keeps in step with the flow;
- * the flow context may carry the first tracer itself.  Contexts on other
- * streams are ordered with events; the next call's record waits for this
- * call's replays. */
+ * (s + 1) x 3 x n_dofs doubles), then the n tracer contexts stepped over
+ * that record, each as sw_tracer_step would (bit for bit).  They take the
+ * step stage by stage together: each stage of up to eight contexts is one
+ * launch that factorises H(zeta^(l)) (eq:mass_matrix_concentration) once
+ * per cell for all of them, on the sample rule.  The tracer contexts must
+ * share the flow's mesh, degree and scheme, one quadrature and one degree
+ * rule (h_lim, adapt_degree), and must not repeat (SW_EINVAL otherwise);
+ * they start each call with the flow's state, which the call keeps in step
+ * with the flow, and carry the flow's bathymetry.  The flow context may
+ * carry the first tracer itself.  Every launch of the call runs on the flow
+ * context's stream, after the tracer contexts' earlier work; their streams
+ * wait for its end. */
 sw_status sw_step_tracers(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, double dt);
 /* Tracers that react with each other: sw_step_tracers with the reactions
  * h phi_k(c_1, ..., c_n) of eq:shw, phi_k = sum_j B_kj c_j, between the n
@@ -420,9 +425,8 @@ sw_status sw_step_tracers(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, doubl
  * depth is taken from the first of them.  Each context's own decay (params.tracer_decay) and diffusion still
  * apply.  Every launch of the call runs on the flow context's stream, after
  * the tracer contexts' earlier work; their streams wait for its end (also
- * after a failure).  A context listed twice, the flow context itself, or
- * tracer contexts of different quadrature (sw_params.quadrature) is
- * SW_EINVAL. */
+ * after a failure).  The contexts' requirements are sw_step_tracers'; the
+ * flow context itself as a tracer context is SW_EINVAL. */
 sw_status sw_step_tracers_react(sw_ctx *flow, int32_t n, sw_ctx *const *tracers, const double *react_host,
                                 double dt);
 
