@@ -101,6 +101,20 @@ hipError_t launch_trc(int r, int P, int mode, const StageArgs& a, int nblk, hipS
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_trc_degree_r1(int P, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_trc_degree_r2(int P, const StageArgs& a, int nblk, hipStream_t s);
+hipError_t launch_trc_degree_r3(int P, const StageArgs& a, int nblk, hipStream_t s);
+
+hipError_t launch_trc_degree(int r, int P, const StageArgs& a, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  switch (r) {
+    case 1: return launch_trc_degree_r1(P, a, nblk, s);
+    case 2: return launch_trc_degree_r2(P, a, nblk, s);
+    case 3: return launch_trc_degree_r3(P, a, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_trc_multi_r1(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
 hipError_t launch_trc_multi_r2(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
 hipError_t launch_trc_multi_r3(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
@@ -981,7 +995,11 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
   const bool replay = tracer && c->rp[0] != nullptr;
   const bool fast_ok = !replay && c->nv == 0;
   const bool trc_replay = replay && fmode == F_STAGE && c->nv == 0;
-  if (fast_ok && tracer && fmode == F_FINAL) {
+  // a replay's final combination: the degree decision on the recorded end
+  // flow, the fast tracer kernel on the cells that keep their degree, the
+  // general kernel (final combination and next start) on the others
+  const bool trc_final = replay && fmode == F_FINAL && c->nv == 0;
+  if ((fast_ok && tracer && fmode == F_FINAL) || trc_final) {
     // the final kernel updates the degree flags; the tracer kernel reads the step's own
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
     HIPCHK(hipGetLastError());
@@ -1015,6 +1033,25 @@ sw_status elements(sw_ctx* c, int fmode, int gmode, int gmode2, int slot, int nt
       StageArgs tr = a;
       tr.need = nullptr;   // every cell
       HIPCHK(launch_trc(c->r, L.P, F_STAGE, tr, L.nblk, c->s));
+      continue;
+    }
+    if (trc_final) {
+      StageArgs d = a;
+      d.need = c->d_need;
+      d.wflag = L.d_wflag;
+      HIPCHK(launch_trc_degree(c->r, L.P, d, L.nblk, c->s));
+      {
+        sw_ctx::Scope sc(c, 6, 1);
+        StageArgs tr = a;
+        tr.need = c->d_need;   // the cells that keep their degree
+        HIPCHK(launch_trc(c->r, L.P, F_FINAL, tr, L.nblk, c->s));
+      }
+      sw_ctx::Scope sc(c, 4, 1);
+      StageArgs g = a;
+      g.need = c->d_need;
+      g.wflag = L.d_wflag;
+      g.nwave = L.nblk;
+      HIPCHK(launch_stage_scan(c->r, L.P, gmode, gmode2, g, std::min(L.nblk, kListGrid), c->s));
       continue;
     }
     StageArgs g = a;

@@ -11,4 +11,8 @@ hipError_t launch_trc_multi_r3(int P, const StageArgs& a, const TrcSet& ts, int 
   return trc_multi_r<3>(P, a, ts, nblk, s);
 }
 
+hipError_t launch_trc_degree_r3(int P, const StageArgs& a, int nblk, hipStream_t s) {
+  return trc_degree_r<3>(P, a, nblk, s);
+}
+
 }  // namespace swk
