@@ -115,17 +115,17 @@ hipError_t launch_trc_degree(int r, int P, const StageArgs& a, int nblk, hipStre
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_trc_multi_r1(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
-hipError_t launch_trc_multi_r2(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
-hipError_t launch_trc_multi_r3(int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi_r1(int P, int mode, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi_r2(int P, int mode, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi_r3(int P, int mode, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
 
-hipError_t launch_trc_multi(int r, int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s) {
+hipError_t launch_trc_multi(int r, int P, int mode, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   if (ts.M < 1 || ts.M > kMaxReact) return hipErrorInvalidValue;
   switch (r) {
-    case 1: return launch_trc_multi_r1(P, a, ts, nblk, s);
-    case 2: return launch_trc_multi_r2(P, a, ts, nblk, s);
-    case 3: return launch_trc_multi_r3(P, a, ts, nblk, s);
+    case 1: return launch_trc_multi_r1(P, mode, a, ts, nblk, s);
+    case 2: return launch_trc_multi_r2(P, mode, a, ts, nblk, s);
+    case 3: return launch_trc_multi_r3(P, mode, a, ts, nblk, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2027,14 +2027,13 @@ sw_status sw_rk_stage(sw_ctx* c, int32_t l) {
   return SW_OK;
 }
 
-sw_status sw_step_end(sw_ctx* c) {
-  if (!c) return fail(SW_EINVAL, "NULL context");
-  if (c->stage_done != c->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
-  // final combination; the same pass prepares the next step's start (slot 0)
-  // (IMEX: explicit, the implicit weights b~ = b)
-  sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2, c->b);
-  if (st != SW_OK) return st;
-  // per-member diagnostics (two-level segmented reduction); advances each member's time
+}  // extern "C"
+
+namespace {
+
+// End of a step after the final combination's launches: per-member
+// diagnostics (two-level segmented reduction), each member's time advanced.
+sw_status step_end_finish(sw_ctx* c) {
   hipLaunchKernelGGL(k_diag_part_seg, dim3(c->ncch), dim3(256), 0, c->s, c->d_cdiag, c->d_flag, c->d_cch,
                      c->d_part);
   HIPCHK(hipGetLastError());
@@ -2046,6 +2045,20 @@ sw_status sw_step_end(sw_ctx* c) {
   c->start_replay = c->rp[0] != nullptr;
   ++c->nstep;
   return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_step_end(sw_ctx* c) {
+  if (!c) return fail(SW_EINVAL, "NULL context");
+  if (c->stage_done != c->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
+  // final combination; the same pass prepares the next step's start (slot 0)
+  // (IMEX: explicit, the implicit weights b~ = b)
+  sw_status st = elements(c, F_FINAL, M_FINAL, M_START, 0, c->ns, c->b, c->ns == 1 ? 1 : 0, 2, c->b);
+  if (st != SW_OK) return st;
+  return step_end_finish(c);
 }
 
 sw_status sw_step(sw_ctx* c, double dt) {
@@ -2222,7 +2235,7 @@ sw_status stage_tracers(sw_ctx* const* tr, int n, int l) {
         ts.tkap[j] = c->p.tracer_decay;
       }
       sw_ctx::Scope sc(g, 5, 1);
-      HIPCHK(launch_trc_multi(g->r, L.P, a, ts, L.nblk, g->s));
+      HIPCHK(launch_trc_multi(g->r, L.P, F_STAGE, a, ts, L.nblk, g->s));
     }
   }
   for (int i = 0; i < n; ++i) {
@@ -2239,6 +2252,8 @@ sw_status stage_tracers(sw_ctx* const* tr, int n, int l) {
 // stage by stage together over the record on the flow's stream (after their
 // earlier work; their streams wait for the call's launches), with the
 // reactions react (n x n, or NULL: none) added after each stage's residuals.
+sw_status final_tracers(sw_ctx* const* tr, int n);
+
 sw_status step_tracers_impl(sw_ctx* flow, int n, sw_ctx* const* tracers, const double* react, double dt) {
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < i; ++j)
@@ -2282,9 +2297,9 @@ sw_status step_tracers_impl(sw_ctx* flow, int n, sw_ctx* const* tracers, const d
     st = stage_tracers(tracers, n, l);
     if (st == SW_OK && react) st = add_reactions(tracers, n, react, l - 1, true);
   }
-  for (int i = 0; i < n && st == SW_OK; ++i) {
-    point(tracers[i], end);
-    st = sw_step_end(tracers[i]);
+  if (st == SW_OK) {
+    for (int i = 0; i < n; ++i) point(tracers[i], end);
+    st = final_tracers(tracers, n);
   }
   for (int i = 0; i < n; ++i) {
     point(tracers[i], nullptr);
@@ -2296,6 +2311,89 @@ sw_status step_tracers_impl(sw_ctx* flow, int n, sw_ctx* const* tracers, const d
   for (int i = 0; i < n; ++i)
     if (own[i] != flow->s) HIPCHK(hipStreamWaitEvent(own[i], flow->ev_rec, 0));
   return st;
+}
+
+// The final combination's StageArgs of one level of a context, as
+// sw_step_end forms them.
+StageArgs final_args(sw_ctx* c, const LevelH& L) {
+  StageArgs a = stage_args(c, L);
+  a.slot = 0;
+  a.nterm = c->ns;
+  for (int m = 0; m < 4; ++m) {
+    a.a[m] = c->b[m];
+    a.at[m] = c->b[m];
+  }
+  a.att = 0.0;
+  a.diag_init = c->ns == 1 ? 1 : 0;
+  return a;
+}
+
+// The final combination of the tracer contexts tr[0..n), whose flow pointers
+// name the record's end: on the sample rule, each context's degree decision
+// on the end flow, then one multi-tracer launch per level and group of at
+// most kMaxReact contexts for the cells that keep their degree (H factorised
+// once), then each context's general kernel on the others and the end of its
+// step; otherwise each context's own sw_step_end.
+sw_status final_tracers(sw_ctx* const* tr, int n) {
+  sw_ctx* c0 = tr[0];
+  if (c0->nv > 0 || c0->rp[0] == nullptr) {
+    for (int i = 0; i < n; ++i) {
+      sw_status st = sw_step_end(tr[i]);
+      if (st != SW_OK) return st;
+    }
+    return SW_OK;
+  }
+  for (int i = 0; i < n; ++i)
+    if (tr[i]->stage_done != tr[i]->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
+  for (int i = 0; i < n; ++i) {
+    sw_ctx* c = tr[i];
+    // the step's own degree flags, read by the tracer kernel
+    hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
+    HIPCHK(hipGetLastError());
+    for (const auto& L : c->lv) {
+      StageArgs d = final_args(c, L);
+      d.need = c->d_need;
+      d.wflag = L.d_wflag;
+      HIPCHK(launch_trc_degree(c->r, L.P, d, L.nblk, c->s));
+    }
+  }
+  // every context takes the same degree decisions (one flow, one degree rule)
+  for (int g0 = 0; g0 < n; g0 += kMaxReact) {
+    const int gn = std::min(kMaxReact, n - g0);
+    sw_ctx* g = tr[g0];
+    for (const auto& L : g->lv) {
+      StageArgs a = final_args(g, L);
+      a.need = g->d_need;
+      TrcSet ts{};
+      ts.M = gn;
+      for (int j = 0; j < gn; ++j) {
+        const sw_ctx* c = tr[g0 + j];
+        ts.res[j] = c->d_res;
+        ts.cn[j] = c->d_cn;
+        ts.c0[j] = c->d_sn[3];
+        for (int f = 0; f < 4; ++f) ts.ss[j][f] = c->d_sn[f];
+        ts.cdiag[j] = c->d_cdiag;
+        ts.tnu[j] = c->p.tracer_diff * c->p.tracer_strain / (double)(c->r * c->r);
+        ts.tkap[j] = c->p.tracer_decay;
+      }
+      sw_ctx::Scope sc(g, 6, 1);
+      HIPCHK(launch_trc_multi(g->r, L.P, F_FINAL, a, ts, L.nblk, g->s));
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    sw_ctx* c = tr[i];
+    for (const auto& L : c->lv) {
+      sw_ctx::Scope sc(c, 4, 1);
+      StageArgs gk = final_args(c, L);
+      gk.need = c->d_need;
+      gk.wflag = L.d_wflag;
+      gk.nwave = L.nblk;
+      HIPCHK(launch_stage_scan(c->r, L.P, M_FINAL, M_START, gk, std::min(L.nblk, kListGrid), c->s));
+    }
+    sw_status st = step_end_finish(c);
+    if (st != SW_OK) return st;
+  }
+  return SW_OK;
 }
 
 }  // namespace

@@ -253,13 +253,13 @@ hipError_t launch_react(int r, const ReactArgs& a, hipStream_t s);
 struct TrcSet {
   int M;
   double* res[kMaxReact];          // residual slots [NS][4][K][NP]
-  const double* cn[kMaxReact];     // C~^n [K][NP]
+  double* cn[kMaxReact];           // C~^n [K][NP]; the final combination writes the next start's
   const double* c0[kMaxReact];     // c^n, the step start's tracer [K][NP]
   double* ss[kMaxReact][4];        // stage state
   double* cdiag[kMaxReact];        // per-cell diagnostics
   double tnu[kMaxReact], tkap[kMaxReact];   // diffusion (C S / r^2) and decay
 };
-hipError_t launch_trc_multi(int r, int P, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
+hipError_t launch_trc_multi(int r, int P, int mode, const StageArgs& a, const TrcSet& ts, int nblk, hipStream_t s);
 hipError_t launch_amr_transfer(const AmrXferArgs& a, hipStream_t s);
 hipError_t launch_amr_raster(const RasterArgs& a, hipStream_t s);
 hipError_t launch_amr_mass(const AmrMassArgs& a, hipStream_t s);
