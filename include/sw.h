@@ -403,7 +403,8 @@ sw_status sw_tracer_step(sw_ctx *c, const double *stages_dev, const double *end_
  * that record, each as sw_tracer_step would (bit for bit).  They take the
  * step stage by stage together: each stage of up to eight contexts is one
  * launch that factorises H(zeta^(l)) (eq:mass_matrix_concentration) once
- * per cell for all of them, on the sample rule.  The tracer contexts must
+ * per cell for all of them, on the sample rule, and so is the final
+ * combination on the cells whose degree the end flow leaves unchanged.  The tracer contexts must
  * share the flow's mesh, degree and scheme, one quadrature and one degree
  * rule (h_lim, adapt_degree), and must not repeat (SW_EINVAL otherwise);
  * they start each call with the flow's state, which the call keeps in step
