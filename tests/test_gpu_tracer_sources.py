@@ -107,19 +107,71 @@ def test_several_tracers_over_one_recorded_flow():
     rec.close()
 
 
-def test_step_tracers_one_call():
-    say("case: sw_step_tracers, a flow context with its own tracer and two more tracers, 12 steps")
+def flooding_case():
+    """The hanging mesh with a 0.6 m bump on the shore: cells flood and dry
+    within a few steps at 0.8 of the first step's bound (on the oracle, the
+    degree-0 count goes 25, 25, 25, 26, 25, 26, ...), so a replay's final
+    combination takes both the cells that keep their degree and those that
+    change it."""
     o, b = hanging_case(2, (16, 8))
+    dof = o.dof_coords()
+    o.init_lake_at_rest(0.6 * np.exp(-((dof[..., 0] - 1400.0) ** 2 + (dof[..., 1] - 1000.0) ** 2) / 200.0 ** 2))
+    return o, b
+
+
+def flooding_dt(s, st):
+    return 0.8 * float(s.apply_operator(st[0], st[1], st[2], st[3], 0.0)[4].cpu()[0])
+
+
+def test_replay_with_degree_changes():
+    say("case: sw_tracer_step over a flooding shore, 12 steps, against the coupled run")
+    o, b = flooding_case()
+    st0 = o.get_state()
+    rec = gpu_from_oracle(o, b)
+    dt = flooding_dt(rec, st0)
+    n = 12
+    ns = rec.n_stages()
+    stages = torch.empty(n, ns, 3, rec.n_dofs, dtype=torch.float64, device="cuda:0")
+    end = torch.empty(n, 3, rec.n_dofs, dtype=torch.float64, device="cuda:0")
+    rec.set_state(*st0)
+    rec.set_time(0.0)
+    r0 = []
+    for k in range(n):
+        rec.step_record(dt, stages[k], end[k])
+        r0.append(rec.diagnostics()["n_r0_cells"])
+    rec.sync()
+    say(f"  dt {dt:.4e}, degree-0 cells after each step: {r0}")
+    assert len(set(r0)) > 1, r0
+    dof = o.dof_coords()
+    oi, _ = flooding_case()
+    rep = gpu_from_oracle(with_sources(oi, tracer_diff=0.33, tracer_strain=0.004, tracer_decay=2e-3), b)
+    st = [st0[0], st0[1], st0[2], 0.5 + 0.3 * np.cos(dof[..., 0] / 300.0)]
+    got = replay(rep, st, stages, end, dt)
+    rep.set_state(*st)
+    rep.set_time(0.0)
+    for _ in range(n):
+        rep.step(dt)
+    rep.sync()
+    ref = rep.get_state()
+    for f in range(4):
+        assert torch.equal(got[f], ref[f]), (f, float((got[f] - ref[f]).abs().max()))
+    rep.close()
+    rec.close()
+
+
+def test_step_tracers_one_call():
+    say("case: sw_step_tracers over a flooding shore, a flow context with its own tracer and two more tracers, 12 steps")
+    o, b = flooding_case()
     st0 = o.get_state()
     flow = gpu_from_oracle(o, b)
-    dt = fixed_dt(flow, st0)
+    dt = flooding_dt(flow, st0)
     dof = o.dof_coords()
     srcs = [dict(tracer_diff=0.33, tracer_strain=0.004, tracer_decay=0.0),
             dict(tracer_diff=0.0, tracer_strain=0.0, tracer_decay=5e-3)]
     inits = [np.where(dof[..., 0] < 1300.0, 1.0, 0.25), 0.5 + 0.3 * np.cos(dof[..., 0] / 300.0)]
     ctxs = []
     for src in srcs:
-        oi, _ = hanging_case(2, (16, 8))
+        oi, _ = flooding_case()
         ctxs.append(gpu_from_oracle(with_sources(oi, **src), b))
     flow.set_state(*st0)
     flow.set_time(0.0)
@@ -127,9 +179,15 @@ def test_step_tracers_one_call():
         t.set_state(st0[0], st0[1], st0[2], c)
         t.set_time(0.0)
     n = 12
+    r0 = []
     for _ in range(n):
         flow.step_tracers(ctxs, dt)
+        r0.append(flow.diagnostics()["n_r0_cells"])
     flow.sync()
+    say(f"  degree-0 cells after each step: {r0}")
+    # cells change degree, so the final combination runs both the shared
+    # tracer kernel and each context's general kernel
+    assert len(set(r0)) > 1, r0
     got = [t.get_state() for t in ctxs]
     # the flow itself equals its plain coupled run; each tracer its own coupled run
     ref = gpu_from_oracle(o, b)
