@@ -2350,20 +2350,22 @@ sw_status final_tracers(sw_ctx* const* tr, int n) {
     // the step's own degree flags, read by the tracer kernel
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
     HIPCHK(hipGetLastError());
-    for (const auto& L : c->lv) {
-      StageArgs d = final_args(c, L);
-      d.need = c->d_need;
-      d.wflag = L.d_wflag;
-      HIPCHK(launch_trc_degree(c->r, L.P, d, L.nblk, c->s));
-    }
   }
-  // every context takes the same degree decisions (one flow, one degree rule)
+  // every context holds the same flags and takes the same degree decisions
+  // (one flow, one degree rule), so the first context's decision (need[],
+  // wflag[]) serves them all
+  for (const auto& L : c0->lv) {
+    StageArgs d = final_args(c0, L);
+    d.need = c0->d_need;
+    d.wflag = L.d_wflag;
+    HIPCHK(launch_trc_degree(c0->r, L.P, d, L.nblk, c0->s));
+  }
   for (int g0 = 0; g0 < n; g0 += kMaxReact) {
     const int gn = std::min(kMaxReact, n - g0);
     sw_ctx* g = tr[g0];
     for (const auto& L : g->lv) {
       StageArgs a = final_args(g, L);
-      a.need = g->d_need;
+      a.need = c0->d_need;
       TrcSet ts{};
       ts.M = gn;
       for (int j = 0; j < gn; ++j) {
@@ -2382,11 +2384,12 @@ sw_status final_tracers(sw_ctx* const* tr, int n) {
   }
   for (int i = 0; i < n; ++i) {
     sw_ctx* c = tr[i];
-    for (const auto& L : c->lv) {
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+      const auto& L = c->lv[l];
       sw_ctx::Scope sc(c, 4, 1);
       StageArgs gk = final_args(c, L);
-      gk.need = c->d_need;
-      gk.wflag = L.d_wflag;
+      gk.need = c0->d_need;
+      gk.wflag = c0->lv[l].d_wflag;
       gk.nwave = L.nblk;
       HIPCHK(launch_stage_scan(c->r, L.P, M_FINAL, M_START, gk, std::min(L.nblk, kListGrid), c->s));
     }
