@@ -5,6 +5,9 @@ hanging quadtree mesh (r = 1, 2, 3), 20 coupled steps (SSP3 and IMEX), and
 further tracers, each with its own diffusion and decay, carried over one
 recorded flow by contexts of their own (sw_tracer_step): several tracers
 on one flow, each equal to its coupled run bit for bit and to the oracle.
+Several tracer contexts stepped by one call (sw_step_tracers, launch groups
+of up to eight) over a flooding shore, where cells change degree, equal
+their coupled runs bit for bit too.
 """
 import numpy as np
 import pytest
@@ -211,3 +214,39 @@ def test_step_tracers_one_call():
         flow.step_tracers([flow], dt)
     flow.close()
     ref.close()
+
+
+def test_step_tracers_two_launch_groups():
+    say("case: sw_step_tracers with ten tracer contexts (launch groups of eight and two) over a flooding shore, 6 steps")
+    o, b = flooding_case()
+    st0 = o.get_state()
+    flow = gpu_from_oracle(o, b)
+    dt = flooding_dt(flow, st0)
+    dof = o.dof_coords()
+    ctxs, inits = [], []
+    for i in range(10):
+        oi, _ = flooding_case()
+        src = dict(tracer_diff=0.1 * (i % 3), tracer_strain=0.004, tracer_decay=1e-3 * i)
+        ctxs.append(gpu_from_oracle(with_sources(oi, **src), b))
+        inits.append(0.5 + 0.3 * np.cos(dof[..., 0] / (200.0 + 30.0 * i)))
+    flow.set_state(*st0)
+    flow.set_time(0.0)
+    for t, c in zip(ctxs, inits):
+        t.set_state(st0[0], st0[1], st0[2], c)
+        t.set_time(0.0)
+    n = 6
+    for _ in range(n):
+        flow.step_tracers(ctxs, dt)
+    flow.sync()
+    got = [t.get_state()[3].clone() for t in ctxs]
+    # each tracer equals its own coupled run, in either launch group
+    for i, (t, c, g) in enumerate(zip(ctxs, inits, got)):
+        t.set_state(st0[0], st0[1], st0[2], c)
+        t.set_time(0.0)
+        for _ in range(n):
+            t.step(dt)
+        t.sync()
+        own = t.get_state()[3]
+        assert torch.equal(g, own), (i, float((g - own).abs().max()))
+        t.close()
+    flow.close()
