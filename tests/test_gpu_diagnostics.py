@@ -1,6 +1,6 @@
 """GPU: the step's diagnostic outputs and failure modes against the oracle
-(positivity violations, Newton iteration counts, constant-mode
-fallbacks, non-finite state), each driven on purpose from the host:
+(positivity violations, Newton iteration counts, constant-mode fallbacks,
+non-finite state), each driven on purpose from the host:
 
 * a perched 1 cm layer stepped at 30 times the positivity bound (Props. 3.2,
   3.3): the (cell, stage) pairs with a negative target mass and the smallest
