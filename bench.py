@@ -50,14 +50,24 @@ CLOCK_HZ = 2.4e9
 VALU_CYCLES = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "element_stage_beach_dambreak_256.traffic.json")
 STAGE_SOURCES = ["sw_stage.inc", "sw_dev.h", "sw_internal.h", "sw_stage_dispatch.inc", "sw_stage_r2.hip"]
+# the fast tracer kernel also inlines the element kernels' helpers
+TRACER_SOURCES = STAGE_SOURCES + ["sw_tracer.inc", "sw_tracer_r3.hip"]
 
 
-def stage_source_sha():
+def source_sha(files):
     h = hashlib.sha256()
-    for f in STAGE_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2505_18743_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def stage_source_sha():
+    return source_sha(STAGE_SOURCES)
+
+
+def tracer_source_sha():
+    return source_sha(TRACER_SOURCES)
 
 
 def element_stage_work(S, r, n_f, stage_terms):
@@ -331,7 +341,7 @@ def quadtree_bench(steps, warmup, device):
         kname = "k_elem" if name == "element_stage" else "k_trc"
         kernel = f"{kname}<r={r},P={'/'.join(str(lanes_for(S)) for S in Ss)},F_STAGE> (one launch per level)"
         counters = read_counters(os.path.join(ROOT, "profiles", f"{name}_tidal_quadtree_r3.traffic.json"),
-                                 stage_source_sha())
+                                 stage_source_sha() if name == "element_stage" else tracer_source_sha())
         # per stage: the launches of all levels together
         roof = roofline(b / calls, f / calls, t_ms * 1e-3 / calls, counters, kernel)
         roof.update(launches=n, scope="all levels of one stage per launch group")
