@@ -2345,9 +2345,10 @@ sw_status final_tracers(sw_ctx* const* tr, int n) {
   }
   for (int i = 0; i < n; ++i)
     if (tr[i]->stage_done != tr[i]->ns) return fail(SW_EINVAL, "all stages must be taken before sw_step_end");
-  for (int i = 0; i < n; ++i) {
-    sw_ctx* c = tr[i];
-    // the step's own degree flags, read by the tracer kernel
+  for (int g0 = 0; g0 < n; g0 += kMaxReact) {
+    sw_ctx* c = tr[g0];
+    // the step's own degree flags, read by the tracer kernel (the flags of a
+    // group's first context stand for the group's)
     hipLaunchKernelGGL(k_copy8, dim3((c->K + 255) / 256), dim3(256), 0, c->s, c->d_flag, c->d_oflag, (size_t)c->K);
     HIPCHK(hipGetLastError());
   }
